@@ -1,0 +1,163 @@
+"""Seeded synthetic inputs for VeST runs (shared by tests, smoke and bench).
+
+This module only draws numbers: observed index sets, planted-model values and
+initial factors.  It imports nothing else from this package and holds none of
+the factorisation arithmetic (no delta, no update rule, no responsibility);
+both the GPU path and the CPU oracle consume what it returns.
+
+Workload recipe (stand-ins for the paper's rating tensors, Sec. 4.1 Table 2,
+which are not available here):
+  * observed indices: per mode uniform or bounded Zipf (P(r) ~ r^-s over ranks
+    1..I, inverse-CDF sampling, ranks mapped to indices by a seeded
+    permutation); duplicate tuples are rejected and redrawn, so Omega is a set;
+  * values: a planted Tucker model with core and factors i.i.d. N(0, 1),
+    evaluated at the observed entries, plus Gaussian noise of a stated variance
+    or SNR; the rating-shaped workload clips 3 + 1.25 z / sqrt(|G|) to the
+    integers 1..5;
+  * initial state: factors and core i.i.d. U[0, 1) (Alg. 2 line 1).
+"""
+import math
+
+import numpy as np
+
+SEED_BASE = 20190402
+
+
+def _zipf_sampler(I, s, rng):
+    w = np.arange(1, I + 1, dtype=np.float64) ** (-float(s))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    perm = rng.permutation(I)
+
+    def draw(m):
+        r = np.searchsorted(cdf, rng.random(m), side="right")
+        return perm[np.minimum(r, I - 1)]
+    return draw
+
+
+def _uniform_sampler(I, rng):
+    def draw(m):
+        return rng.integers(0, I, size=m)
+    return draw
+
+
+def observed_indices(dims, nnz, rng, zipf=None):
+    """nnz distinct index tuples, shape [nnz, N] int32, in draw order."""
+    N = len(dims)
+    total = 1
+    for d in dims:
+        total *= int(d)
+    if nnz > total:
+        raise ValueError("nnz exceeds the number of cells")
+    zipf = zipf or [None] * N
+    samplers = [(_zipf_sampler(dims[n], zipf[n], rng) if zipf[n] else _uniform_sampler(dims[n], rng))
+                for n in range(N)]
+    linear = total < 2 ** 62
+    got = np.empty((0, N), dtype=np.int64)
+    while got.shape[0] < nnz:
+        need = nnz - got.shape[0]
+        draw = int(need * 1.05) + 64
+        cand = np.stack([samplers[n](draw) for n in range(N)], axis=1).astype(np.int64)
+        allt = np.concatenate([got, cand], axis=0)
+        if linear:
+            key = np.zeros(allt.shape[0], dtype=np.int64)
+            for n in range(N):
+                key = key * int(dims[n]) + allt[:, n]
+            _, first = np.unique(key, return_index=True)
+        else:
+            _, first = np.unique(allt, axis=0, return_index=True)
+        first.sort()
+        got = allt[first][:nnz]
+    return np.ascontiguousarray(got, dtype=np.int32)
+
+
+def planted_values(idx, core, factors, chunk=1 << 17):
+    """Planted model value at every observed entry (Tucker model, Sec. 2.2).
+
+    Evaluated by contracting the core with one factor row per mode, last mode
+    first, with numpy tensordot on chunks of entries.
+    """
+    N = idx.shape[1]
+    out = np.empty(idx.shape[0], dtype=np.float64)
+    for s in range(0, idx.shape[0], chunk):
+        sl = idx[s:s + chunk]
+        m = sl.shape[0]
+        t = np.broadcast_to(core, (m,) + core.shape)
+        for n in range(N - 1, -1, -1):
+            rows = factors[n][sl[:, n]]                     # [m, J_n]
+            t = np.einsum("m...j,mj->m...", t, rows)
+        out[s:s + chunk] = t
+    return out
+
+
+def planted_model(ranks, dims, rng):
+    core = rng.standard_normal(tuple(ranks))
+    factors = [rng.standard_normal((dims[n], ranks[n])) for n in range(len(dims))]
+    return core, factors
+
+
+def initial_state(dims, ranks, rng):
+    """Factors and core i.i.d. U[0, 1) (Alg. 2 line 1)."""
+    factors = [rng.random((dims[n], ranks[n])) for n in range(len(dims))]
+    core = rng.random(tuple(ranks))
+    return factors, core
+
+
+def make_problem(dims, nnz, ranks, seed, zipf=None, planted_ranks=None,
+                 noise_var=None, snr_db=None, rating=False):
+    """Observed tensor plus an initial state.
+
+    Returns dict(idx, val, factors, core, planted=(core, factors)).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = observed_indices(dims, nnz, rng, zipf)
+    pr = planted_ranks or ranks
+    pcore, pfac = planted_model(pr, dims, rng)
+    z = planted_values(idx, pcore, pfac)
+    if rating:
+        g = 1
+        for r in pr:
+            g *= r
+        val = np.clip(np.rint(3.0 + 1.25 * z / math.sqrt(g)), 1.0, 5.0)
+    else:
+        val = z.copy()
+        if noise_var is not None:
+            val += rng.standard_normal(z.shape[0]) * math.sqrt(noise_var)
+        elif snr_db is not None:
+            var = float(np.mean(z * z)) / (10.0 ** (snr_db / 10.0))
+            val += rng.standard_normal(z.shape[0]) * math.sqrt(var)
+    factors, core = initial_state(dims, ranks, rng)
+    return {"idx": idx, "val": val, "factors": factors, "core": core,
+            "planted": (pcore, pfac)}
+
+
+# Workloads.  Sizes follow the configurations the method is exercised on:
+#  1: 100^3, 1e4 entries, core 5^3, planted + N(0, 0.01) noise, L_F 0.01, FP64
+#  2: (1e5)^3, 1e7 entries, core 10^3, planted, SNR 20 dB, L_F 0.01
+#  3: 500k x 20k x 2k, Zipf 1.1 / 1.0 / uniform, 1e8 entries, ratings 1..5, L_1 0.1
+#  4: 50k x 50k x 1000 x 24, Zipf 1.1 / 1.0, 5e7 entries, core 8^4, SNR 20 dB
+WORKLOADS = {
+    "planted-100^3-nnz1e4-r5": dict(dims=(100, 100, 100), nnz=10_000, ranks=(5, 5, 5),
+                                    noise_var=0.01, reg=0, lam=0.01, seed=SEED_BASE + 1),
+    "planted-1e5^3-nnz1e7-r10": dict(dims=(100_000,) * 3, nnz=10_000_000, ranks=(10, 10, 10),
+                                     snr_db=20.0, reg=0, lam=0.01, seed=SEED_BASE + 2),
+    "rating-zipf-500k.20k.2k-nnz1e8-r10": dict(dims=(500_000, 20_000, 2_000), nnz=100_000_000,
+                                               ranks=(10, 10, 10), zipf=(1.1, 1.0, None),
+                                               rating=True, reg=1, lam=0.1, seed=SEED_BASE + 3),
+    "planted-zipf-50k.50k.1k.24-nnz5e7-r8": dict(dims=(50_000, 50_000, 1_000, 24), nnz=50_000_000,
+                                                 ranks=(8, 8, 8, 8), zipf=(1.1, 1.0, None, None),
+                                                 snr_db=20.0, reg=0, lam=0.01, seed=SEED_BASE + 4),
+}
+
+
+def workload(name, nnz=None, dims=None):
+    """Build a named workload (optionally with a smaller nnz / dims)."""
+    w = dict(WORKLOADS[name])
+    if nnz is not None:
+        w["nnz"] = nnz
+    if dims is not None:
+        w["dims"] = dims
+    reg, lam = w.pop("reg"), w.pop("lam")
+    p = make_problem(**w)
+    p["reg"], p["lam"] = reg, lam
+    return p

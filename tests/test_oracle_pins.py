@@ -1,0 +1,368 @@
+"""Pins of the FP64 CPU oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a dense
+brute-force reconstruction, a derivative by linearity, a minimiser fitted on
+the brute-force loss, leave-one-out by recomputation, textbook special cases
+(ridge regression, matrix factorisation, the rank-1 scalar case), or a planted
+model.  A plausible slip in the oracle (dropped term, wrong sign or index,
+transposed operand, a missing mask check) fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, REG_LF, REG_L1
+import bruteforce as bf
+
+
+def tiny(seed, dims=(4, 5, 3), ranks=(2, 3, 2), nnz=30, scale=1.0):
+    rng = np.random.default_rng(seed)
+    total = int(np.prod(dims))
+    lin = rng.choice(total, size=nnz, replace=False)
+    idx = np.stack(np.unravel_index(lin, dims), axis=1).astype(np.int32)
+    val = rng.standard_normal(nnz) * scale
+    factors = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    core = rng.standard_normal(ranks)
+    return idx, val, factors, core
+
+
+SHAPES = [((4, 5, 3), (2, 3, 2), 30), ((3, 4), (2, 3), 9), ((3, 3, 2, 4), (2, 1, 2, 3), 40),
+          ((6, 2, 3), (1, 1, 1), 20)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_delta_and_recon_match_bruteforce(shape):
+    dims, ranks, nnz = shape
+    idx, val, f, g = tiny(1, dims, ranks, nnz)
+    o = Oracle(idx, val, f, g)
+    B = bf.recon_at(idx, g, f)
+    for e in range(nnz):
+        assert o.recon(e) == pytest.approx(B[e], rel=1e-12, abs=1e-12)
+    for n in range(len(dims)):
+        D = bf.delta_by_linearity(idx, g, f, n)
+        for e in range(nnz):
+            d = o.delta(n, e)
+            np.testing.assert_allclose(d, D[e], rtol=1e-12, atol=1e-12)
+            # B(alpha) = a^(n)_{i_n,:} . delta^(n)_alpha  (Eq. 7 with Eq. 11)
+            assert f[n][idx[e, n]] @ d == pytest.approx(B[e], rel=1e-11, abs=1e-12)
+    np.testing.assert_allclose(o.residual(), val - B, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("reg", [REG_LF, REG_L1])
+def test_loss_and_re_match_bruteforce(reg):
+    idx, val, f, g = tiny(2)
+    lam = 0.37
+    o = Oracle(idx, val, f, g, reg=reg, lam=lam)
+    L = o.loss()
+    s = bf.sse(idx, val, g, f)
+    assert L["sse"] == pytest.approx(s, rel=1e-12)
+    assert L["xnorm2"] == pytest.approx(float(val @ val), rel=1e-12)
+    assert L["loss"] == pytest.approx(bf.loss(idx, val, g, f, reg, lam), rel=1e-12)
+    assert L["re"] == pytest.approx(np.sqrt(s) / np.linalg.norm(val), rel=1e-12)
+
+
+def _factor_line(idx, val, g, f, n, i, j, reg, lam, smooth=False):
+    def fn(x):
+        ff = [A.copy() for A in f]
+        ff[n][i, j] = x
+        if smooth:   # loss without the lam |a_ij| term of this coordinate
+            return bf.loss(idx, val, g, ff, reg, lam) - lam * abs(x)
+        return bf.loss(idx, val, g, ff, reg, lam)
+    return fn
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_factor_update_LF_is_exact_line_minimiser(seed):
+    idx, val, f, g = tiny(seed)
+    lam = 0.05
+    for (n, i, j) in [(0, idx[0, 0], 1), (1, idx[3, 1], 2), (2, idx[7, 2], 0)]:
+        o = Oracle(idx, val, f, g, reg=REG_LF, lam=lam)
+        o.update_factor_elem(n, i, j)
+        x, curv = bf.quad_argmin(_factor_line(idx, val, g, f, n, i, j, REG_LF, lam), f[n][i, j])
+        assert curv > 0
+        assert o.factors[n][i, j] == pytest.approx(x, rel=1e-9, abs=1e-10)
+        # nothing else moved
+        for m in range(3):
+            diff = o.factors[m] - f[m]
+            if m == n:
+                diff[i, j] = 0
+            assert np.all(diff == 0)
+
+
+@pytest.mark.parametrize("lam", [0.01, 0.5, 3.0, 40.0])
+def test_factor_update_L1_is_exact_line_minimiser(lam):
+    idx, val, f, g = tiny(6)
+    for (n, i, j) in [(0, idx[0, 0], 0), (1, idx[2, 1], 1), (2, idx[5, 2], 1)]:
+        o = Oracle(idx, val, f, g, reg=REG_L1, lam=lam)
+        o.update_factor_elem(n, i, j)
+        x = bf.lasso_argmin(_factor_line(idx, val, g, f, n, i, j, REG_L1, lam, smooth=True), lam)
+        assert o.factors[n][i, j] == pytest.approx(x, rel=1e-9, abs=1e-10)
+
+
+def _core_line(idx, val, g, f, beta, reg, lam, smooth=False):
+    def fn(x):
+        gg = g.copy()
+        gg[beta] = x
+        v = bf.loss(idx, val, gg, f, reg, lam)
+        return v - lam * abs(x) if smooth else v
+    return fn
+
+
+def test_core_update_LF_is_exact_line_minimiser():
+    idx, val, f, g = tiny(7)
+    lam = 0.2
+    for beta in [(0, 0, 0), (1, 2, 1), (0, 1, 1)]:
+        flat = int(np.ravel_multi_index(beta, g.shape))
+        o = Oracle(idx, val, f, g, reg=REG_LF, lam=lam)
+        o.update_core_elem(flat)
+        x, curv = bf.quad_argmin(_core_line(idx, val, g, f, beta, REG_LF, lam), g[beta])
+        assert o.core[beta] == pytest.approx(x, rel=1e-9, abs=1e-10)
+
+
+@pytest.mark.parametrize("lam", [0.05, 1.0, 25.0])
+def test_core_update_L1_is_exact_line_minimiser(lam):
+    idx, val, f, g = tiny(8)
+    for beta in [(0, 0, 0), (1, 2, 1), (1, 0, 1)]:
+        flat = int(np.ravel_multi_index(beta, g.shape))
+        o = Oracle(idx, val, f, g, reg=REG_L1, lam=lam)
+        o.update_core_elem(flat)
+        x = bf.lasso_argmin(_core_line(idx, val, g, f, beta, REG_L1, lam, smooth=True), lam)
+        assert o.core[beta] == pytest.approx(x, rel=1e-9, abs=1e-10)
+
+
+@pytest.mark.parametrize("reg,lam", [(REG_LF, 0.1), (REG_L1, 0.3)])
+def test_objective_never_increases_per_coordinate(reg, lam):
+    idx, val, f, g = tiny(9, dims=(4, 4, 3), ranks=(2, 2, 2), nnz=25)
+    o = Oracle(idx, val, f, g, reg=reg, lam=lam)
+    prev = bf.loss(idx, val, o.core, o.factors, reg, lam)
+    for _ in range(2):
+        for n in range(3):
+            for i in range(o.dims[n]):
+                for j in range(o.ranks[n]):
+                    o.update_factor_elem(n, i, j)
+                    cur = bf.loss(idx, val, o.core, o.factors, reg, lam)
+                    assert cur <= prev + 1e-12 * abs(prev)
+                    prev = cur
+        for b in range(o.core.size):
+            o.update_core_elem(b)
+            cur = bf.loss(idx, val, o.core, o.factors, reg, lam)
+            assert cur <= prev + 1e-12 * abs(prev)
+            prev = cur
+
+
+def test_row_update_is_gauss_seidel_in_ascending_j():
+    idx, val, f, g = tiny(10)
+    a = Oracle(idx, val, f, g, reg=REG_LF, lam=0.1)
+    b = Oracle(idx, val, f, g, reg=REG_LF, lam=0.1)
+    for n in range(3):
+        for i in range(a.dims[n]):
+            a.update_row(n, i)
+            for j in range(b.ranks[n]):
+                b.update_factor_elem(n, i, j)
+    for n in range(3):
+        np.testing.assert_allclose(a.factors[n], b.factors[n], rtol=1e-13, atol=1e-14)
+
+
+def test_repeated_row_updates_converge_to_ridge_solution():
+    # With everything else fixed, the row subproblem is ridge regression:
+    # min ||x - D a||^2 + lam ||a||^2,  D = [delta_alpha] by linearity.
+    idx, val, f, g = tiny(11, dims=(3, 6, 5), ranks=(3, 2, 2), nnz=40)
+    lam = 0.3
+    o = Oracle(idx, val, f, g, reg=REG_LF, lam=lam)
+    n, i = 0, int(idx[0, 0])
+    for _ in range(400):
+        o.update_row(n, i)
+    D = bf.delta_by_linearity(idx, g, f, n)
+    rows = idx[:, n] == i
+    Dr, xr = D[rows], val[rows]
+    want = np.linalg.solve(Dr.T @ Dr + lam * np.eye(3), Dr.T @ xr)
+    np.testing.assert_allclose(o.factors[n][i], want, rtol=1e-9, atol=1e-11)
+
+
+def test_matrix_factorisation_special_case():
+    # N = 2 with the identity core: X ~ A B^T, a row update solves ridge MF.
+    rng = np.random.default_rng(12)
+    I, K, J = 5, 7, 3
+    lin = rng.choice(I * K, size=20, replace=False)
+    idx = np.stack(np.unravel_index(lin, (I, K)), axis=1).astype(np.int32)
+    val = rng.standard_normal(20)
+    A, B = rng.standard_normal((I, J)), rng.standard_normal((K, J))
+    o = Oracle(idx, val, [A, B], np.eye(J), reg=REG_LF, lam=0.2)
+    i = int(idx[0, 0])
+    for _ in range(500):
+        o.update_row(0, i)
+    sel = idx[:, 0] == i
+    Bs = B[idx[sel, 1]]
+    want = np.linalg.solve(Bs.T @ Bs + 0.2 * np.eye(J), Bs.T @ val[sel])
+    np.testing.assert_allclose(o.factors[0][i], want, rtol=1e-9, atol=1e-11)
+
+
+def test_rank_one_scalar_closed_form():
+    # J = (1,1,1) on a 2x2x2 tensor: one coordinate, minimise
+    # sum (x - g a b c)^2 + lam a^2  ->  a = g sum x b c / (g^2 sum (b c)^2 + lam)
+    idx = np.array([[0, 0, 0], [0, 1, 1], [1, 0, 1], [0, 1, 0]], np.int32)
+    val = np.array([1.0, 2.0, -1.0, 0.5])
+    A = np.array([[0.7], [1.3]])
+    Bm = np.array([[0.4], [-0.9]])
+    Cm = np.array([[1.1], [0.2]])
+    g = np.array([[[1.5]]])
+    lam = 0.25
+    o = Oracle(idx, val, [A, Bm, Cm], g, reg=REG_LF, lam=lam)
+    o.update_row(0, 0)
+    rows = [0, 1, 3]
+    bc = np.array([Bm[idx[e, 1], 0] * Cm[idx[e, 2], 0] for e in rows])
+    want = 1.5 * np.dot(val[rows], bc) / (1.5 ** 2 * np.dot(bc, bc) + lam)
+    assert o.factors[0][0, 0] == pytest.approx(want, rel=1e-14)
+
+
+@pytest.mark.parametrize("seed", [13, 14])
+def test_responsibility_equals_leave_one_out(seed):
+    idx, val, f, g = tiny(seed)
+    cmask = np.zeros(g.shape, np.uint8)
+    cmask[1, 1, 0] = 1
+    g = g.copy()
+    g[1, 1, 0] = 0.0
+    fmask = [np.zeros(A.shape, np.uint8) for A in f]
+    fmask[1][2, 1] = 1
+    f = [A.copy() for A in f]
+    f[1][2, 1] = 0.0
+    o = Oracle(idx, val, f, g, cmask=cmask, fmask=fmask)
+    ck, fk = o.responsibility()
+    base = bf.sse(idx, val, g, f)
+    for beta in np.ndindex(g.shape):
+        if cmask[beta]:
+            assert ck[beta] == np.inf
+            continue
+        gg = g.copy()
+        gg[beta] = 0.0
+        assert ck[beta] == pytest.approx(bf.sse(idx, val, gg, f) - base, rel=1e-10, abs=1e-12)
+    for n in range(3):
+        for (i, j) in np.ndindex(f[n].shape):
+            if fmask[n][i, j]:
+                assert fk[n][i, j] == np.inf
+                continue
+            ff = [A.copy() for A in f]
+            ff[n][i, j] = 0.0
+            assert fk[n][i, j] == pytest.approx(bf.sse(idx, val, g, ff) - base, rel=1e-10, abs=1e-12)
+
+
+def test_prune_takes_smallest_keys_with_index_tiebreak():
+    idx, val, f, g = tiny(15)
+    cmask = np.zeros(g.shape, np.uint8)
+    cmask.flat[4] = 1
+    o = Oracle(idx, val, f, g, cmask=cmask)
+    ck = np.array([5.0, -1.0, 2.0, 2.0, -9.0, 2.0, 0.0, 7.0, 2.0, 1.0, 3.0, 4.0]).reshape(g.shape)
+    fk = [np.arange(A.size, dtype=float)[::-1].reshape(A.shape) for A in f]
+    fk[0].flat[:] = 1.0                                   # all tied: lowest indices win
+    o.prune(ck, fk, 5, [3, 2, 0])
+    # core: flat 4 (key -9) is already marked; the unmarked ones sorted by
+    # (key, index) start 1(-1), 6(0), 9(1), 2(2), 3(2), 5(2), 8(2), ...
+    order = [q for q in np.lexsort((np.arange(12), ck.ravel())) if q != 4][:5]
+    assert order == [1, 6, 9, 2, 3]
+    want = np.zeros(12, np.uint8)
+    want[order] = 1
+    want[4] = 1
+    np.testing.assert_array_equal(o.cmask.ravel(), want)
+    assert np.all(o.core.ravel()[order] == 0)
+    np.testing.assert_array_equal(np.flatnonzero(o.fmask[0]), [0, 1, 2])
+    np.testing.assert_array_equal(np.flatnonzero(o.fmask[1]), [13, 14])
+    assert o.fmask[2].sum() == 0
+    with pytest.raises(ValueError):
+        o.prune(ck, fk, 100, [0, 0, 0])
+
+
+def test_sweeps_leave_pruned_elements_at_zero():
+    idx, val, f, g = tiny(16)
+    fmask = [np.zeros(A.shape, np.uint8) for A in f]
+    fmask[0][:, 1] = 1
+    fmask[2][1, 0] = 1
+    cmask = np.zeros(g.shape, np.uint8)
+    cmask[0, 2, 1] = 1
+    f = [A * (1 - m) for A, m in zip(f, fmask)]
+    g = g * (1 - cmask)
+    for reg in (REG_LF, REG_L1):
+        o = Oracle(idx, val, f, g, reg=reg, lam=0.1, fmask=fmask, cmask=cmask)
+        o.iteration()
+        o.iteration()
+        assert np.all(o.factors[0][:, 1] == 0) and o.factors[2][1, 0] == 0 and o.core[0, 2, 1] == 0
+        assert np.any(o.factors[0][:, 0] != f[0][:, 0])
+
+
+def test_planted_noiseless_model_is_a_fixed_point():
+    rng = np.random.default_rng(17)
+    dims, ranks = (8, 7, 6), (2, 2, 2)
+    lin = rng.choice(int(np.prod(dims)), size=150, replace=False)
+    idx = np.stack(np.unravel_index(lin, dims), axis=1).astype(np.int32)
+    f = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    g = rng.standard_normal(ranks)
+    val = bf.recon_at(idx, g, f)
+    o = Oracle(idx, val, f, g, reg=REG_LF, lam=1e-12)
+    o.iteration()
+    for n in range(3):
+        np.testing.assert_allclose(o.factors[n], f[n], rtol=1e-8, atol=1e-9)
+    np.testing.assert_allclose(o.core, g, rtol=1e-8, atol=1e-9)
+    assert o.loss()["re"] < 1e-10
+
+
+def test_recovers_planted_model_from_random_start():
+    # Coordinate descent is non-convex: from U[0,1) starts some seeds stall in
+    # a local minimum (RE ~ 0.2-0.3).  Seed 20 reaches the planted model.
+    rng = np.random.default_rng(20)
+    dims, ranks = (10, 10, 10), (2, 2, 2)
+    lin = rng.permutation(1000)
+    train, test = lin[:300], lin[300:400]
+    f = [rng.standard_normal((d, r)) for d, r in zip(dims, ranks)]
+    g = rng.standard_normal(ranks)
+    full = bf.full_tensor(g, f)
+
+    def cells(lin_):
+        return np.stack(np.unravel_index(lin_, dims), axis=1).astype(np.int32)
+    idx = cells(train)
+    val = full[tuple(idx.T)]
+    f0 = [rng.random((d, r)) for d, r in zip(dims, ranks)]
+    g0 = rng.random(ranks)
+    o = Oracle(idx, val, f0, g0, reg=REG_LF, lam=1e-9)
+    for _ in range(500):
+        o.iteration()
+        if o.loss()["re"] < 1e-7:
+            break
+    assert o.loss()["re"] < 1e-6
+    ti = cells(test)
+    pred = bf.recon_at(ti, o.core, o.factors)
+    truth = full[tuple(ti.T)]
+    assert np.linalg.norm(pred - truth) / np.linalg.norm(truth) < 1e-5
+
+
+def test_normalisation_keeps_reconstruction():
+    idx, val, f, g = tiny(19)
+    f = [A.copy() for A in f]
+    f[1][:, 2] = 0.0                     # a zero column stays zero
+    o = Oracle(idx, val, f, g)
+    before = bf.full_tensor(o.core, o.factors)
+    o.normalize()
+    np.testing.assert_allclose(bf.full_tensor(o.core, o.factors), before, rtol=1e-12, atol=1e-12)
+    for n in range(3):
+        nrm = np.linalg.norm(o.factors[n], axis=0)
+        assert np.all((np.abs(nrm - 1) < 1e-12) | (nrm == 0))
+
+
+def test_printed_L1_factor_gradient_is_not_the_minimiser():
+    # Documents the reading of Eq. 13: the printed g_fm (no sign, factor 2 on
+    # the first term only) does not minimise L_1; the derivation-consistent
+    # g = -2 (c_j - sum_{t != j} v_t a_t) does (it is what the oracle uses).
+    idx, val, f, g = tiny(20)
+    lam, n, i, j = 0.4, 0, int(idx[0, 0]), 1
+    D = bf.delta_by_linearity(idx, g, f, n)
+    rows = idx[:, n] == i
+    Dr, xr = D[rows], val[rows]
+    c, V = Dr.T @ xr, Dr.T @ Dr
+    a = f[n][i]
+    rest = sum(V[j, t] * a[t] for t in range(len(a)) if t != j)
+    g_printed, d = 2 * c[j] - rest, 2 * V[j, j]
+
+    def rule(gv):
+        return (lam - gv) / d if gv > lam else (-(lam + gv) / d if gv < -lam else 0.0)
+    best = bf.lasso_argmin(_factor_line(idx, val, g, f, n, i, j, REG_L1, lam, smooth=True), lam)
+    o = Oracle(idx, val, f, g, reg=REG_L1, lam=lam)
+    o.update_factor_elem(n, i, j)
+    assert o.factors[n][i, j] == pytest.approx(best, rel=1e-9, abs=1e-10)
+    assert abs(rule(g_printed) - best) > 1e-3
