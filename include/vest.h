@@ -1,0 +1,155 @@
+/*
+ * vest.h -- C ABI of the MI355X (gfx950) VeST hot-path library, libvest.so.
+ *
+ * VeST (M. Park, J.-G. Jang, L. Sael, "VeST: Very Sparse Tucker Factorization
+ * of Large-Scale Tensors", arXiv:1904.02603) fits a partially observed N-order
+ * tensor X (observed entries Omega) with a Tucker model: core G (J_1 x .. x
+ * J_N) and factor matrices A^(n) (I_n x J_n), minimising Eq. 1 (L_F) or Eq. 2
+ * (L_1) by element-wise coordinate descent (Sec. 3.4), and prunes elements of
+ * low responsibility (Sec. 3.2-3.3).  This library runs the per-iteration
+ * steps of Alg. 2 on the GPU; the host decides the schedule.
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller, except where
+ *     a comment says "host".  The library never frees caller memory.
+ *   - Indices are 0-based.  idx is entry-major: idx[e*N + n] is the mode-n
+ *     index of observed entry e; entry e is "canonical entry id" e.
+ *   - Factor matrices are row-major FP64: A_n[i*J_n + j] = a^(n)_{i j}.
+ *   - The core is row-major FP64 with the last mode fastest: the flat index of
+ *     (j_1..j_N) is ((j_1*J_2 + j_2)*J_3 + j_3)... ("flat order").
+ *   - Marking table (Sec. 3.3): factor_mask[n][i] bit j set = a^(n)_{ij}
+ *     pruned; core_mask[flat] != 0 = core element pruned.  Pruned elements are
+ *     zero and are never updated again.
+ *   - Every call enqueues on the stream given to vest_init and returns without
+ *     waiting, except vest_init and vest_loss, which synchronise that stream.
+ *   - Return value: VEST_OK (0) or a negative VEST_E* code; vest_last_error()
+ *     gives a message for the last failing call on the calling thread.
+ *   - A context is not thread-safe.  Distinct contexts on distinct streams are
+ *     independent.
+ */
+#ifndef VEST_H
+#define VEST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VEST_MAX_ORDER 10
+#define VEST_MAX_RANK 32
+
+enum {
+    VEST_OK = 0,
+    VEST_EINVAL = -1,   /* bad argument or input data (nothing of the caller's was modified) */
+    VEST_ENOSPC = -2,   /* workspace too small                                         */
+    VEST_EDEVICE = -3,  /* HIP runtime error; the context must be destroyed             */
+    VEST_ESTATE = -4,   /* call out of order (e.g. vest_prune before vest_responsibility) */
+    VEST_EUNSUPPORTED = -5 /* valid problem, but no kernel instance for this (order, rank) */
+};
+
+enum { VEST_REG_LF = 0, VEST_REG_L1 = 1 };   /* Eq. 1 / Eq. 2 */
+
+/* Arithmetic of the delta contraction and of the row / residual sums.  The
+ * per-coordinate division, the soft threshold and the responsibility keys
+ * are FP64 in every form; factors and core stay FP64. */
+enum { VEST_FP64 = 0, VEST_FP32 = 1 };
+
+typedef struct {
+    int32_t order;                     /* N, 2..VEST_MAX_ORDER                         */
+    int32_t reg;                       /* VEST_REG_LF or VEST_REG_L1                   */
+    int32_t precision;                 /* VEST_FP64 or VEST_FP32                       */
+    int32_t reserved;                  /* must be 0                                    */
+    double lambda;                     /* lambda > 0, one value for core and factors
+                                          (Eq. 1 / Eq. 2, Table 1)                     */
+    int64_t nnz;                       /* |Omega| >= 1                                 */
+    int64_t dims[VEST_MAX_ORDER];      /* I_n >= 1, I_n < 2^31                         */
+    int32_t ranks[VEST_MAX_ORDER];     /* J_n, 1..VEST_MAX_RANK                        */
+} vest_desc;
+
+typedef struct vest_ctx vest_ctx;      /* opaque, library-owned host object */
+
+/* Upper bound of the device workspace vest_init needs for this problem
+ * (indices re-laid out per mode, residuals, reduction scratch, sort scratch).
+ * Depends only on the descriptor, so a scheduler can admit jobs by footprint.
+ * Needs a HIP device (the sort scratch size is queried from the runtime). */
+int vest_workspace_bytes(const vest_desc *desc, size_t *bytes /* host out */);
+
+/* Validate the observed tensor and build the per-mode layouts of Omega
+ * (Omega^{(n)}_{i_n} of Table 1: entries grouped by their mode-n index, ties
+ * in canonical id order) inside the workspace.
+ *   idx          nnz*N int32, entry-major (read during the call only)
+ *   val          nnz FP64 observed values X_alpha (read during the call only)
+ *   factors      host array of N device pointers, A_n with I_n*J_n FP64;
+ *                in: initial values (Alg. 2 line 1), out: the model state
+ *   core         prod(J_n) FP64, in/out
+ *   factor_mask  host array of N device pointers, I_n uint32 words each
+ *                (requires J_n <= 32); may hold earlier marks (resume)
+ *   core_mask    prod(J_n) bytes
+ *   workspace    >= vest_workspace_bytes(desc) bytes, 256-byte aligned,
+ *                owned by the caller, used exclusively by this context
+ * Fails with VEST_EINVAL (index out of range, duplicate index tuple -- Omega is
+ * a set --, non-finite value, lambda <= 0, bad order/rank) before writing any
+ * caller buffer other than the workspace.  On success, marked elements of the
+ * factors and core are set to zero.  Synchronises the stream.
+ * stream is a hipStream_t (NULL = the default stream). */
+int vest_init(const vest_desc *desc, void *stream,
+              const int32_t *idx, const double *val,
+              double *const *factors, double *core,
+              uint32_t *const *factor_mask, uint8_t *core_mask,
+              void *workspace, size_t ws_bytes, vest_ctx **out /* host out */);
+
+/* One pass of Alg. 4 for mode n: every row i of A^(n) is updated element by
+ * element, j ascending, Gauss-Seidel in place, skipping marked elements, with
+ * Eq. 9 (L_F) or Eq. 13 (L_1, soft threshold).  Rows are independent, so the
+ * result equals the sequential sweep. */
+int vest_sweep_factor(vest_ctx *ctx, int32_t mode);
+
+/* One pass of the core update: every unmarked core element in flat order,
+ * sequentially (Sec. 3.5), with Eq. 12 (L_F) or Eq. 14 (L_1).  Executed as an
+ * exact block Gauss-Seidel (same sequence of one-dimensional minimisations,
+ * different rounding). */
+int vest_sweep_core(vest_ctx *ctx);
+
+/* Responsibility keys of every element from one snapshot of the state
+ * (Sec. 3.2, Eq. 5 and Eq. 6), as Delta(e) = SSE(with e set to 0) - SSE =
+ * ||X||^2 (RE(e)^2 - RE^2), which orders elements exactly as Resp(e) of
+ * Eq. 3 does when RE > 0.  Marked elements get +infinity.
+ *   core_key     prod(J_n) FP64 out
+ *   factor_key   host array of N device pointers, I_n*J_n FP64 out each
+ * The buffers must stay valid until the next vest_prune. */
+int vest_responsibility(vest_ctx *ctx, double *core_key, double *const *factor_key);
+
+/* Prune (Sec. 3.3, Alg. 3 last step): in the core and in each factor matrix
+ * independently, zero and mark the k unmarked elements with the smallest
+ * (key, flat index) of the last vest_responsibility call.
+ *   factor_k     host array of N counts.
+ * VEST_ESTATE if no keys are pending; VEST_EINVAL if a count is negative or
+ * exceeds that tensor's unmarked elements. */
+int vest_prune(vest_ctx *ctx, int64_t core_k, const int64_t *factor_k);
+
+/* Loss and normalised reconstruction error of the current state (Eq. 1 /
+ * Eq. 2, Eq. 4; ||X|| over Omega):
+ *   out[0] SSE = sum_Omega (X - B)^2    out[1] ||X||^2 over Omega
+ *   out[2] regulariser term             out[3] loss = out[0] + out[2]
+ *   out[4] RE = sqrt(out[0] / out[1])
+ * out is a host array of 5 doubles.  Synchronises the stream. */
+int vest_loss(vest_ctx *ctx, double *out);
+
+/* Layout statistics of mode n (host out, 8 values): slots, padding slots,
+ * waves, long rows, long-row chunks, max row length, rows, nnz. */
+int vest_layout_stats(vest_ctx *ctx, int32_t mode, int64_t *out);
+
+/* Release the context (not the workspace or any caller buffer).  Waits for
+ * the context's queued work. */
+int vest_destroy(vest_ctx *ctx);
+
+const char *vest_strerror(int code);
+const char *vest_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VEST_H */

@@ -1,0 +1,448 @@
+// Entry points of the C ABI declared in include/vest.h.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace vest {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+static int device_error(vest_ctx *c, hipError_t e, const char *where)
+{
+    set_error("%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+    if (c) c->dead = true;
+    return VEST_EDEVICE;
+}
+
+static int check_desc(const vest_desc *d)
+{
+    if (!d) { set_error("null descriptor"); return VEST_EINVAL; }
+    if (d->order < 2 || d->order > VEST_MAX_ORDER) { set_error("order %d outside 2..%d", d->order, VEST_MAX_ORDER); return VEST_EINVAL; }
+    if (d->reg != VEST_REG_LF && d->reg != VEST_REG_L1) { set_error("unknown regulariser %d", d->reg); return VEST_EINVAL; }
+    if (d->precision != VEST_FP64 && d->precision != VEST_FP32) { set_error("unknown precision %d", d->precision); return VEST_EINVAL; }
+    if (d->reserved != 0) { set_error("reserved field must be 0"); return VEST_EINVAL; }
+    if (!(d->lambda > 0.0) || !std::isfinite(d->lambda)) { set_error("lambda must be finite and > 0"); return VEST_EINVAL; }
+    if (d->nnz < 1 || d->nnz >= (int64_t(1) << 31)) { set_error("nnz %lld outside 1..2^31-1", (long long)d->nnz); return VEST_EINVAL; }
+    for (int n = 0; n < d->order; ++n) {
+        if (d->dims[n] < 1 || d->dims[n] >= (int64_t(1) << 31)) { set_error("dims[%d] out of range", n); return VEST_EINVAL; }
+        if (d->ranks[n] < 1 || d->ranks[n] > VEST_MAX_RANK) { set_error("ranks[%d] outside 1..%d", n, VEST_MAX_RANK); return VEST_EINVAL; }
+    }
+    for (int n = 1; n < d->order; ++n)
+        if (d->ranks[n] != d->ranks[0]) {
+            set_error("unequal ranks are not supported by the compiled kernels");
+            return VEST_EUNSUPPORTED;
+        }
+    int64_t G = 1;
+    for (int n = 0; n < d->order; ++n) G *= d->ranks[n];
+    for (int n = 0; n < d->order; ++n)
+        if (d->dims[n] * d->ranks[n] >= (int64_t(1) << 31) || G >= (int64_t(1) << 31)) {
+            set_error("tensor of %d-th factor or core too large", n);
+            return VEST_EINVAL;
+        }
+    if (!shape_supported(d->order, d->ranks[0])) {
+        set_error("no kernel instance for order %d, rank %d", d->order, d->ranks[0]);
+        return VEST_EUNSUPPORTED;
+    }
+    return VEST_OK;
+}
+
+int plan_workspace(const vest_desc *d, Plan *p)
+{
+    const int N = d->order, J = d->ranks[0];
+    const int64_t nnz = d->nnz;
+    int64_t G = 1, Imax = 0, maxt = 0;
+    for (int n = 0; n < N; ++n) {
+        G *= J;
+        Imax = d->dims[n] > Imax ? d->dims[n] : Imax;
+        maxt = d->dims[n] * J > maxt ? d->dims[n] * J : maxt;
+    }
+    maxt = G > maxt ? G : maxt;
+    p->max_tensor = maxt;
+    for (int n = 0; n < N; ++n) {
+        p->slot_bound[n] = nnz + nnz / 8 + 1024 * kLaneTarget + 1024;
+        p->wave_bound[n] = d->dims[n] / 64 + nnz / 512 + 16;
+        p->long_bound[n] = nnz / kChunk + 1;
+    }
+    p->chunk_bound = nnz / 1024 + 1;
+    p->gram_chunks = (d->dims[N - 1] + kGramRows - 1) / kGramRows;
+    size_t t1 = 0, t2 = 0;
+    hipError_t e1 = hipcub::DeviceRadixSort::SortPairs(nullptr, t1, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                       (uint32_t *)nullptr, (uint32_t *)nullptr, (int)nnz);
+    hipError_t e2 = hipcub::DeviceRadixSort::SortPairs(nullptr, t2, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                                       (uint32_t *)nullptr, (uint32_t *)nullptr, (int)maxt);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        set_error("radix-sort scratch query failed (no HIP device?)");
+        return VEST_EDEVICE;
+    }
+    p->sort_tmp = (t1 > t2 ? t1 : t2) + 256;
+    p->scratch_bytes = (size_t)nnz * 4 * 5 + (size_t)Imax * (4 + 16 + 8) + 8 + 16 * 256;
+    return VEST_OK;
+}
+
+// Assign every workspace region (also used with base = nullptr to size it).
+static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
+{
+    const int N = c->N, J = c->J;
+    const size_t ts = (size_t)c->tsize;
+    bool ok = true;
+    auto take = [&](size_t bytes) {
+        void *q = b.take(bytes ? bytes : 1);
+        ok = ok && (q != nullptr || b.base == nullptr);
+        return q;
+    };
+    for (int n = 0; n < N; ++n) {
+        ModeLayout &L = c->lay[n];
+        const int64_t sb = p.slot_bound[n];
+        L.nslots = sb;
+        L.nwaves = (int32_t)p.wave_bound[n];
+        L.nlong = (int32_t)p.long_bound[n];
+        L.nchunks = (int32_t)p.chunk_bound;
+        L.waves = (WaveInfo *)take(p.wave_bound[n] * sizeof(WaveInfo));
+        L.row_order = (int32_t *)take(c->d.dims[n] * 4);
+        for (int m = 0; m < N - 1; ++m) L.oidx[m] = (int32_t *)take(sb * 4);
+        L.xval = take(sb * ts);
+        L.perm = (int32_t *)take(sb * 4);
+        L.eslot = n < N - 1 ? (int32_t *)take(sb * 4) : nullptr;
+        L.longrows = (LongRow *)take(p.long_bound[n] * sizeof(LongRow));
+    }
+    c->e = take(p.slot_bound[N - 1] * ts);
+    for (int n = 0; n < N; ++n) c->Gp[n] = take(c->G * ts);
+    for (int n = 0; n < N; ++n)
+        c->A32[n] = c->d.precision == VEST_FP32 ? (float *)take(c->d.dims[n] * J * 4) : nullptr;
+    for (int m = 0; m + 2 < N; ++m) c->colA[m] = take(c->d.dims[m] * J * ts);
+    const int gw = gram_width(J);
+    const int64_t Il = c->d.dims[N - 1];
+    c->rowbuf = (double *)take(Il * gw * 8);
+    c->kp = (double *)take(Il * gw * 8);
+    c->gram_part = (double *)take(p.gram_chunks * gw * gw * 8);
+    c->gram = (double *)take(gw * gw * 8);
+    c->dprev = (double *)take(J * J * 8);
+    const int na = nacc_vc(J) > 2 * J ? nacc_vc(J) : 2 * J;
+    c->partials = (double *)take(p.chunk_bound * na * 8);
+    c->red = (double *)take((16 * kLossBlocks + 64) * 8);
+    c->flags = (int32_t *)take(64);
+    c->pk_in = (uint64_t *)take(p.max_tensor * 8);
+    c->pk_out = (uint64_t *)take(p.max_tensor * 8);
+    c->pv_in = (uint32_t *)take(p.max_tensor * 4);
+    c->pv_out = (uint32_t *)take(p.max_tensor * 4);
+    c->sort_tmp = take(p.sort_tmp);
+    c->sort_tmp_bytes = p.sort_tmp;
+    *scratch = (char *)take(p.scratch_bytes);
+    return ok;
+}
+
+static void fill_ctx_shape(vest_ctx *c, const vest_desc *d)
+{
+    c->d = *d;
+    c->N = d->order;
+    c->J = d->ranks[0];
+    c->G = 1;
+    for (int n = 0; n < c->N; ++n) c->G *= c->J;
+    c->tsize = d->precision == VEST_FP32 ? 4 : 8;
+}
+
+#define CALL_HIP(c, x, where)                                       \
+    do {                                                            \
+        hipError_t e_ = (x);                                        \
+        if (e_ != hipSuccess) return device_error((c), e_, where); \
+    } while (0)
+
+static int ensure_gp(vest_ctx *c, int mode)
+{
+    if (c->gp_version[mode] != c->core_version) {
+        CALL_HIP(c, launch_permute_core(c, mode), "permute core");
+        c->gp_version[mode] = c->core_version;
+    }
+    return VEST_OK;
+}
+
+// Refresh every mode's permuted core right after the core changed, so that a
+// factor sweep launches exactly one kernel.
+static int refresh_gp(vest_ctx *c)
+{
+    for (int n = 0; n < c->N; ++n) {
+        int rc = ensure_gp(c, n);
+        if (rc) return rc;
+    }
+    return VEST_OK;
+}
+
+static int ensure_a32(vest_ctx *c)
+{
+    if (c->d.precision != VEST_FP32) return VEST_OK;
+    for (int n = 0; n < c->N; ++n)
+        if (!c->a32_valid[n]) {
+            CALL_HIP(c, launch_cast_factor(c, n), "cast factor");
+            c->a32_valid[n] = true;
+        }
+    return VEST_OK;
+}
+
+static int ensure_residual(vest_ctx *c)
+{
+    if (c->e_valid) return VEST_OK;
+    int rc = ensure_a32(c);
+    if (rc) return rc;
+    rc = ensure_gp(c, c->N - 1);
+    if (rc) return rc;
+    CALL_HIP(c, launch_rowgroup(c, c->N - 1, OP_RESID), "residual");
+    c->e_valid = true;
+    return VEST_OK;
+}
+
+static int live(vest_ctx *c)
+{
+    if (!c) { set_error("null context"); return VEST_EINVAL; }
+    if (c->dead) { set_error("context is unusable after a device error"); return VEST_EDEVICE; }
+    return VEST_OK;
+}
+
+}  // namespace vest
+
+using namespace vest;
+
+extern "C" {
+
+const char *vest_strerror(int code)
+{
+    switch (code) {
+    case VEST_OK: return "ok";
+    case VEST_EINVAL: return "invalid argument or input data";
+    case VEST_ENOSPC: return "workspace too small";
+    case VEST_EDEVICE: return "HIP device error";
+    case VEST_ESTATE: return "call out of order";
+    case VEST_EUNSUPPORTED: return "no kernel instance for this order and rank";
+    default: return "unknown error";
+    }
+}
+
+const char *vest_last_error(void) { return g_err; }
+
+int vest_workspace_bytes(const vest_desc *desc, size_t *bytes)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!bytes) { set_error("null output"); return VEST_EINVAL; }
+    Plan p;
+    rc = plan_workspace(desc, &p);
+    if (rc) return rc;
+    vest_ctx tmp;
+    fill_ctx_shape(&tmp, desc);
+    Bump b{nullptr, 0, ~size_t(0)};
+    char *scr = nullptr;
+    carve(&tmp, p, b, &scr);
+    *bytes = b.off + 256;
+    return VEST_OK;
+}
+
+int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const double *val, double *const *factors,
+              double *core, uint32_t *const *factor_mask, uint8_t *core_mask, void *workspace, size_t ws_bytes,
+              vest_ctx **out)
+{
+    int rc = check_desc(desc);
+    if (rc) return rc;
+    if (!out || !idx || !val || !factors || !core || !factor_mask || !core_mask || !workspace) {
+        set_error("null pointer argument");
+        return VEST_EINVAL;
+    }
+    for (int n = 0; n < desc->order; ++n)
+        if (!factors[n] || !factor_mask[n]) { set_error("null factor or mask pointer (mode %d)", n); return VEST_EINVAL; }
+    if (((uintptr_t)workspace & 255) != 0) { set_error("workspace must be 256-byte aligned"); return VEST_EINVAL; }
+    Plan p;
+    rc = plan_workspace(desc, &p);
+    if (rc) return rc;
+    size_t need = 0;
+    {
+        vest_ctx tmp;
+        fill_ctx_shape(&tmp, desc);
+        Bump b{nullptr, 0, ~size_t(0)};
+        char *scr = nullptr;
+        carve(&tmp, p, b, &scr);
+        need = b.off + 256;
+    }
+    if (ws_bytes < need) {
+        set_error("workspace of %zu bytes, %zu needed", ws_bytes, need);
+        return VEST_ENOSPC;
+    }
+    vest_ctx *c = new (std::nothrow) vest_ctx();
+    if (!c) { set_error("out of host memory"); return VEST_EINVAL; }
+    fill_ctx_shape(c, desc);
+    c->stream = (hipStream_t)stream;
+    hipError_t he = hipGetDevice(&c->device);
+    if (he != hipSuccess) { int r = device_error(nullptr, he, "hipGetDevice"); delete c; return r; }
+    for (int n = 0; n < c->N; ++n) {
+        c->A[n] = factors[n];
+        c->fmask[n] = factor_mask[n];
+    }
+    c->core = core;
+    c->cmask = core_mask;
+    Bump b{(char *)workspace, 0, ws_bytes};
+    char *scratch = nullptr;
+    if (!carve(c, p, b, &scratch)) { delete c; set_error("workspace carve failed"); return VEST_ENOSPC; }
+
+    int bad = 0;
+    he = build_layouts(c, idx, val, scratch, p.scratch_bytes, &bad);
+    if (he != hipSuccess) { int r = device_error(nullptr, he, "layout"); delete c; return r; }
+    if (bad) {
+        const char *why[] = {"", "index out of range", "non-finite value", "duplicate index tuple (Omega is a set)"};
+        set_error("invalid observed tensor: %s", why[bad]);
+        delete c;
+        return VEST_EINVAL;
+    }
+    // ||X||^2 over Omega
+    double *dout = c->red + 16 * kLossBlocks;
+    he = launch_sumsq(c->stream, val, desc->nnz, c->red, dout);
+    double hx[2] = {0, 0};
+    if (he == hipSuccess) he = hipMemcpyAsync(hx, dout, 16, hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) { int r = device_error(nullptr, he, "norm"); delete c; return r; }
+    c->xnorm2 = hx[0];
+
+    // marking table: zero the marked elements, count the marks
+    int64_t *cnt = reinterpret_cast<int64_t *>(c->red + 16 * kLossBlocks + 8);
+    int64_t hc[VEST_MAX_ORDER + 1] = {};
+    he = hipMemsetAsync(cnt, 0, (c->N + 1) * 8, c->stream);
+    if (he == hipSuccess) he = launch_mask_init(c, cnt);
+    if (he == hipSuccess) he = hipMemcpyAsync(hc, cnt, (c->N + 1) * 8, hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(c->rowbuf, 0, c->d.dims[c->N - 1] * gram_width(c->J) * 8, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) { int r = device_error(nullptr, he, "masks"); delete c; return r; }
+    for (int n = 0; n < c->N; ++n) c->marked_fac[n] = hc[n];
+    c->marked_core = hc[c->N];
+    c->core_version = 1;
+    for (int n = 0; n < c->N; ++n) c->a32_valid[n] = false;
+    if ((rc = ensure_a32(c)) || (rc = refresh_gp(c))) { delete c; return rc; }
+    *out = c;
+    return VEST_OK;
+}
+
+int vest_sweep_factor(vest_ctx *c, int32_t mode)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (mode < 0 || mode >= c->N) { set_error("mode %d outside 0..%d", mode, c->N - 1); return VEST_EINVAL; }
+    if ((rc = ensure_a32(c))) return rc;
+    if ((rc = ensure_gp(c, mode))) return rc;
+    CALL_HIP(c, launch_rowgroup(c, mode, OP_SWEEP), "factor sweep");
+    c->e_valid = false;
+    return VEST_OK;
+}
+
+int vest_sweep_core(vest_ctx *c)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if ((rc = ensure_residual(c))) return rc;
+    CALL_HIP(c, launch_core_sweep(c), "core sweep");
+    c->core_version++;
+    c->e_valid = true;
+    return refresh_gp(c);
+}
+
+int vest_responsibility(vest_ctx *c, double *core_key, double *const *factor_key)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!core_key || !factor_key) { set_error("null key pointer"); return VEST_EINVAL; }
+    for (int n = 0; n < c->N; ++n)
+        if (!factor_key[n]) { set_error("null factor key pointer (mode %d)", n); return VEST_EINVAL; }
+    if ((rc = ensure_residual(c))) return rc;
+    for (int n = 0; n < c->N; ++n) {
+        c->key_fac[n] = factor_key[n];
+        if ((rc = ensure_gp(c, n))) return rc;
+        CALL_HIP(c, launch_rowgroup(c, n, OP_KEYS), "factor keys");
+    }
+    c->key_core = core_key;
+    CALL_HIP(c, launch_core_keys(c, core_key), "core keys");
+    c->keys_pending = true;
+    return VEST_OK;
+}
+
+int vest_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!c->keys_pending) { set_error("vest_prune needs keys from vest_responsibility"); return VEST_ESTATE; }
+    if (!factor_k) { set_error("null factor counts"); return VEST_EINVAL; }
+    if (core_k < 0 || core_k > c->G - c->marked_core) { set_error("core count %lld out of range", (long long)core_k); return VEST_EINVAL; }
+    for (int n = 0; n < c->N; ++n)
+        if (factor_k[n] < 0 || factor_k[n] > c->d.dims[n] * c->J - c->marked_fac[n]) {
+            set_error("factor count %lld of mode %d out of range", (long long)factor_k[n], n);
+            return VEST_EINVAL;
+        }
+    if (core_k > 0) {
+        CALL_HIP(c, launch_prune(c, -1, core_k), "prune core");
+        c->marked_core += core_k;
+        c->core_version++;
+    }
+    for (int n = 0; n < c->N; ++n)
+        if (factor_k[n] > 0) {
+            CALL_HIP(c, launch_prune(c, n, factor_k[n]), "prune factor");
+            c->marked_fac[n] += factor_k[n];
+            c->a32_valid[n] = false;
+        }
+    c->e_valid = false;
+    c->keys_pending = false;
+    if ((rc = ensure_a32(c))) return rc;
+    return refresh_gp(c);
+}
+
+int vest_loss(vest_ctx *c, double *out)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!out) { set_error("null output"); return VEST_EINVAL; }
+    if ((rc = ensure_residual(c))) return rc;
+    double *dout = c->red + 16 * kLossBlocks;
+    CALL_HIP(c, launch_loss(c, dout), "loss");
+    double h[2];
+    CALL_HIP(c, hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, c->stream), "loss copy");
+    CALL_HIP(c, hipStreamSynchronize(c->stream), "loss sync");
+    out[0] = h[0];
+    out[1] = c->xnorm2;
+    out[2] = c->d.lambda * h[1];
+    out[3] = out[0] + out[2];
+    out[4] = c->xnorm2 > 0 ? std::sqrt(out[0] / c->xnorm2) : 0.0;
+    return VEST_OK;
+}
+
+int vest_layout_stats(vest_ctx *c, int32_t mode, int64_t *out)
+{
+    if (!c || !out || mode < 0 || mode >= c->N) { set_error("bad argument"); return VEST_EINVAL; }
+    const ModeLayout &L = c->lay[mode];
+    out[0] = L.nslots;
+    out[1] = L.npad;
+    out[2] = L.nwaves;
+    out[3] = L.nlong;
+    out[4] = L.nchunks;
+    out[5] = L.maxlen;
+    out[6] = c->d.dims[mode];
+    out[7] = c->d.nnz;
+    return VEST_OK;
+}
+
+int vest_destroy(vest_ctx *c)
+{
+    if (!c) return VEST_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    delete c;
+    if (e != hipSuccess) return device_error(nullptr, e, "destroy");
+    return VEST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Device-side building blocks shared by the libvest kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace vest {
+
+// Minimiser along one coordinate of  den x^2 - 2 num x + penalty(x)
+// (the element-wise rules of Sec. 3.4, always in FP64):
+//   L_F (Eq. 9 / Eq. 12): num / (den + lambda)
+//   L_1 (Eq. 13 / Eq. 14): soft threshold with g = -2 num, d = 2 den.
+__device__ __forceinline__ double coord_min(int reg, double lambda, double num, double den)
+{
+    if (reg == VEST_REG_LF) return num / (den + lambda);
+    const double g = -2.0 * num, d = 2.0 * den;
+    if (g > lambda) return (lambda - g) / d;
+    if (g < -lambda) return -(lambda + g) / d;
+    return 0.0;
+}
+
+// Index of (t, u), t <= u, in a packed upper triangle of a J x J matrix.
+template <int J>
+__host__ __device__ constexpr int sym(int t, int u)
+{
+    return t <= u ? t * J - t * (t - 1) / 2 + (u - t) : u * J - u * (u - 1) / 2 + (t - u);
+}
+
+// fma for both compute types
+__device__ __forceinline__ double vfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float vfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Contraction of one core slice with the rows of the other modes
+// (Eq. 11): for the slice G[j_n, ...] of the mode-n-permuted core,
+//   sum over (o_0 .. o_{NO-1}) of G[o_0, .., o_{NO-1}] * prod_m r[m][o_m],
+// innermost mode first.  All offsets are compile-time constants; G is a
+// wave-uniform pointer, so the core operands come through scalar loads.
+template <int NO, int J, int D, typename T>
+__device__ __forceinline__ T contract(const T *__restrict__ G, const T (&r)[NO][J])
+{
+    if constexpr (D == NO - 1) {
+        T acc = G[0] * r[D][0];
+#pragma unroll
+        for (int o = 1; o < J; ++o) acc = vfma(G[o], r[D][o], acc);
+        return acc;
+    } else {
+        constexpr int stride = ipow(J, NO - 1 - D);
+        T acc = contract<NO, J, D + 1, T>(G, r) * r[D][0];
+#pragma unroll
+        for (int o = 1; o < J; ++o) acc = vfma(contract<NO, J, D + 1, T>(G + o * stride, r), r[D][o], acc);
+        return acc;
+    }
+}
+
+// delta_alpha^{(n)} (Eq. 11) for one entry, given the permuted core Gp
+// ([J_n][others ascending], row-major) and the N-1 other-mode factor rows.
+template <int N, int J, typename T>
+__device__ __forceinline__ void delta_vec(const T *__restrict__ Gp, const T (&r)[N - 1][J], T (&d)[J])
+{
+    constexpr int slice = ipow(J, N - 1);
+#pragma unroll
+    for (int j = 0; j < J; ++j) d[j] = contract<N - 1, J, 0, T>(Gp + j * slice, r);
+}
+
+// Load a factor row of J values with the widest aligned vector loads.
+template <int J, typename T>
+__device__ __forceinline__ void load_row(const T *__restrict__ p, T (&r)[J])
+{
+    constexpr int bytes = J * (int)sizeof(T);
+    if constexpr (bytes % 16 == 0) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(__builtin_assume_aligned(p, 16));
+#pragma unroll
+        for (int v = 0; v < bytes / 16; ++v) {
+            uint4 x = q[v];
+            __builtin_memcpy(reinterpret_cast<char *>(r) + 16 * v, &x, 16);
+        }
+    } else if constexpr (bytes % 8 == 0) {
+        const uint2 *q = reinterpret_cast<const uint2 *>(__builtin_assume_aligned(p, 8));
+#pragma unroll
+        for (int v = 0; v < bytes / 8; ++v) {
+            uint2 x = q[v];
+            __builtin_memcpy(reinterpret_cast<char *>(r) + 8 * v, &x, 8);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < J; ++v) r[v] = p[v];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor_t(T v, int m)
+{
+    return __shfl_xor(v, m, kWave);
+}
+
+// Sum NA per-lane accumulators over the 2^glog lanes of each row group
+// (xor butterfly: every lane of the group ends with the group total, summed
+// in an order fixed by lane positions).
+template <int NA, typename T>
+__device__ __forceinline__ void group_reduce(T (&s)[NA], int glog)
+{
+    for (int b = 0; b < glog; ++b) {
+        const int m = 1 << b;
+#pragma unroll
+        for (int v = 0; v < NA; ++v) s[v] += shfl_xor_t(s[v], m);
+    }
+}
+
+// Long-row chunk: lane 0 stores the wave total (double) as one partial.
+template <int NA, typename T>
+__device__ __forceinline__ void store_partial(double *__restrict__ part, int chunk, const T (&s)[NA], int lane)
+{
+    if (lane == 0) {
+        double *p = part + (int64_t)chunk * NA;
+#pragma unroll
+        for (int v = 0; v < NA; ++v) p[v] = (double)s[v];
+    }
+}
+
+// Fixed-order sum of the partials of one long row into LDS (one wave);
+// afterwards lane 0 can read all NA values.
+template <int NA>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ part, const LongRow &lr,
+                                             double *__restrict__ lds, int lane)
+{
+    for (int v = lane; v < NA; v += kWave) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int c = 0;
+        for (; c + 4 <= lr.nchunks; c += 4) {
+            const double *p = part + (int64_t)(lr.first_chunk + c) * NA + v;
+            s0 += p[0];
+            s1 += p[NA];
+            s2 += p[2 * NA];
+            s3 += p[3 * NA];
+        }
+        for (; c < lr.nchunks; ++c) s0 += part[(int64_t)(lr.first_chunk + c) * NA + v];
+        lds[v] = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
+}
+
+}  // namespace vest

@@ -1,0 +1,185 @@
+// Internal declarations of libvest (not part of the C ABI).
+//
+// Data layout in HBM (per context, all inside the caller's workspace):
+//
+//  * Per mode n, a "row-group" layout of Omega grouped by the mode-n index
+//    (Omega^{(n)}_{i_n}, Table 1).  Rows are grouped into classes by length:
+//    a row of L entries gets g = 2^c lanes of one 64-lane wavefront, the
+//    smallest power of two with ceil(L / g) <= kLaneTarget; 64/g rows share a
+//    wave.  Inside a class rows are ordered by decreasing length, so the lanes
+//    of a wave carry nearly equal work.  Rows longer than 64 * kLaneTarget are
+//    cut into chunks of 64 * kLaneTarget entries, one wave each, whose partial
+//    sums are combined in a fixed order by a finishing kernel.
+//    Entry (k, lane) of wave w lives in slot waves[w].base + 64 k + lane, so
+//    the k-th entries of the 64 lanes are contiguous: every index / value load
+//    of a wave is one coalesced 256-byte (or 512-byte) transaction.  Lane l of
+//    a row group takes the row's entries l, l + g, l + 2g, ...  Padding slots
+//    carry -1 in the first index array.
+//  * Per slot: the N-1 other-mode indices (int32, one array per mode, modes
+//    ascending), the value X_alpha (double or float), the canonical entry id.
+//  * The residual e = X - B lives in the slot order of mode N-1 (the "core
+//    layout"); other modes carry the slot of each entry in that layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <type_traits>
+
+#include "vest.h"
+
+// (order, uniform rank) pairs with compiled kernel instances.
+#define VEST_SHAPES(X) X(2, 2) X(2, 3) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 8) X(3, 10) \
+    X(4, 2) X(4, 3) X(4, 8)
+
+namespace vest {
+
+constexpr int kWave = 64;
+constexpr int kLaneTarget = 32;                   // entries per lane in a row group
+constexpr int kChunk = kWave * kLaneTarget;       // entries per long-row chunk
+constexpr int kGramRows = 128;                    // rows per gram partial
+constexpr int kLossBlocks = 1024;                 // fixed grid of the loss reductions
+
+struct WaveInfo {
+    int64_t base;   // slot of (k = 0, lane 0)
+    int32_t K;      // entries per lane (trip count)
+    int32_t glog;   // log2(lanes per row), 0..6
+    int32_t first;  // position in row_order of the wave's first row
+    int32_t nrows;  // rows in this wave
+    int32_t chunk;  // long-row chunk id (partial slot) or -1
+    int32_t pad_;
+};
+static_assert(sizeof(WaveInfo) == 32, "WaveInfo layout");
+
+struct LongRow {
+    int32_t row;
+    int32_t first_chunk;
+    int32_t nchunks;
+    int32_t pad_;
+};
+
+struct ModeLayout {
+    int64_t nslots = 0;
+    int64_t npad = 0;
+    int32_t nwaves = 0;
+    int32_t nlong = 0;
+    int32_t nchunks = 0;
+    int64_t maxlen = 0;
+    WaveInfo *waves = nullptr;
+    int32_t *row_order = nullptr;
+    int32_t *oidx[VEST_MAX_ORDER] = {};
+    void *xval = nullptr;
+    int32_t *perm = nullptr;
+    int32_t *eslot = nullptr;
+    LongRow *longrows = nullptr;
+};
+
+// Operations of the row-group kernel.
+enum RowOp { OP_SWEEP = 0, OP_KEYS = 1, OP_RESID = 2, OP_SLAB = 3, OP_APPLY = 4 };
+
+// Number of per-row accumulators of an operation.
+__host__ __device__ constexpr int nacc_vc(int J) { return J * (J + 1) / 2 + J; }
+__host__ __device__ constexpr int round8(int x) { return (x + 7) / 8 * 8; }
+__host__ __device__ constexpr int gram_width(int J) { return round8(nacc_vc(J)); }
+
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+}  // namespace vest
+
+// The context (opaque in the C ABI).
+struct vest_ctx {
+    vest_desc d{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int N = 0, J = 0;                 // uniform rank of the kernel instance
+    int64_t G = 0;                    // |G|
+    int tsize = 8;                    // bytes of the compute type
+
+    // caller-owned model state
+    double *A[VEST_MAX_ORDER] = {};
+    double *core = nullptr;
+    uint32_t *fmask[VEST_MAX_ORDER] = {};
+    uint8_t *cmask = nullptr;
+
+    // workspace-resident derived state
+    vest::ModeLayout lay[VEST_MAX_ORDER];
+    void *e = nullptr;                // residual, core-layout slot order (T)
+    void *Gp[VEST_MAX_ORDER] = {};    // core permuted for each mode (T)
+    float *A32[VEST_MAX_ORDER] = {};  // FP32 copies of the factors (FP32 form)
+    void *colA[VEST_MAX_ORDER] = {};  // column-major factor copies, modes < N-2 (T)
+    double *rowbuf = nullptr;         // [I_{N-1}][gram_width]
+    double *kp = nullptr;             // [I_{N-1}][gram_width]
+    double *gram_part = nullptr;      // [nchunks][gw*gw]
+    double *gram = nullptr;           // [gw*gw]
+    double *dprev = nullptr;          // [J*J] last slab's core change
+    double *partials = nullptr;       // long-row chunk partials
+    double *red = nullptr;            // reduction scratch [4 * kLossBlocks + 16]
+    int32_t *flags = nullptr;         // device error flags [16]
+    uint64_t *pk_in = nullptr, *pk_out = nullptr;  // prune keys
+    uint32_t *pv_in = nullptr, *pv_out = nullptr;  // prune positions
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    double *host_red = nullptr;       // pinned host mirror of small results
+
+    // bookkeeping
+    double xnorm2 = 0.0;
+    int64_t marked_core = 0;
+    int64_t marked_fac[VEST_MAX_ORDER] = {};
+    uint64_t core_version = 1;
+    uint64_t gp_version[VEST_MAX_ORDER] = {};
+    bool a32_valid[VEST_MAX_ORDER] = {};
+    bool e_valid = false;
+    bool keys_pending = false;
+    double *key_core = nullptr;
+    double *key_fac[VEST_MAX_ORDER] = {};
+    bool dead = false;
+};
+
+namespace vest {
+
+// ---------------------------------------------------------------- launchers
+// (defined in the .hip files; return hipSuccess or the first HIP error)
+bool shape_supported(int N, int J);
+
+hipError_t launch_rowgroup(vest_ctx *c, int mode, int op);       // OP_SWEEP / OP_KEYS / OP_RESID
+hipError_t launch_core_sweep(vest_ctx *c);
+hipError_t launch_core_keys(vest_ctx *c, double *core_key);
+hipError_t launch_permute_core(vest_ctx *c, int mode);
+hipError_t launch_cast_factor(vest_ctx *c, int mode);
+hipError_t launch_loss(vest_ctx *c, double *dev_out3);          // sse, reg (device)
+hipError_t launch_prune(vest_ctx *c, int tensor, int64_t k);     // tensor -1 = core
+hipError_t launch_sumsq(hipStream_t s, const double *v, int64_t n, double *partial, double *out);
+hipError_t launch_mask_init(vest_ctx *c, int64_t *counts_dev);
+hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, char *scratch,
+                         size_t scratch_bytes, int *bad);
+
+// ---------------------------------------------------------------- workspace
+struct Plan {
+    size_t total = 0;
+    size_t scratch_bytes = 0;     // init-time scratch
+    size_t sort_tmp = 0;          // radix-sort scratch
+    int64_t slot_bound[VEST_MAX_ORDER] = {};
+    int64_t wave_bound[VEST_MAX_ORDER] = {};
+    int64_t long_bound[VEST_MAX_ORDER] = {};
+    int64_t chunk_bound = 0;
+    int64_t gram_chunks = 0;
+    int64_t max_tensor = 0;
+};
+int plan_workspace(const vest_desc *d, Plan *p);
+
+// Bump allocator over the workspace.
+struct Bump {
+    char *base;
+    size_t off, cap;
+    void *take(size_t bytes) {
+        size_t o = (off + 255) & ~size_t(255);
+        if (o + bytes > cap) return nullptr;
+        off = o + bytes;
+        return base + o;
+    }
+};
+
+void set_error(const char *fmt, ...);
+
+}  // namespace vest

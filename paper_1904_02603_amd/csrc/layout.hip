@@ -1,0 +1,345 @@
+// Validation of the observed tensor and construction of the per-mode
+// row-group layouts (set-up, not part of a sweep).
+//
+//  1. index bounds and finiteness of every value;
+//  2. Omega is a set (Table 1): a stable LSD radix sort by (i_1..i_N) puts
+//     equal tuples next to each other;
+//  3. per mode n: stable radix sort of the entry ids by i_n (ties keep the
+//     canonical id order), row lengths, then the host assigns rows to
+//     row-group classes and waves (see internal.h), and a scatter kernel
+//     writes every entry into its slot.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace vest {
+
+struct DimsArg {
+    int64_t d[VEST_MAX_ORDER];
+    int32_t N;
+};
+
+struct RowPlace {
+    int64_t base;  // normal row: wave base slot; long row: index of its first wave
+    int32_t glog;  // lanes per row (log2); -1 for a long row
+    int32_t sub;   // row group within the wave
+};
+
+struct OidxArg {
+    int32_t *p[VEST_MAX_ORDER];
+};
+
+__global__ void __launch_bounds__(256) k_validate(const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                                  int64_t nnz, DimsArg dm, int32_t *__restrict__ flags)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        for (int n = 0; n < dm.N; ++n) {
+            const int32_t v = idx[e * dm.N + n];
+            if (v < 0 || (int64_t)v >= dm.d[n]) atomicOr(&flags[0], 1);
+        }
+        if (!isfinite(val[e])) atomicOr(&flags[1], 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_iota(uint32_t *__restrict__ v, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) v[q] = (uint32_t)q;
+}
+
+__global__ void __launch_bounds__(256) k_gather_key(const int32_t *__restrict__ idx, int N, int n,
+                                                    const uint32_t *__restrict__ perm, int64_t nnz,
+                                                    uint32_t *__restrict__ keys)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) keys[q] = (uint32_t)idx[(int64_t)perm[q] * N + n];
+}
+
+__global__ void __launch_bounds__(256) k_dupcheck(const int32_t *__restrict__ idx, int N,
+                                                  const uint32_t *__restrict__ perm, int64_t nnz,
+                                                  int32_t *__restrict__ flags)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < 1 || q >= nnz) return;
+    const int32_t *a = idx + (int64_t)perm[q] * N;
+    const int32_t *b = idx + (int64_t)perm[q - 1] * N;
+    bool same = true;
+    for (int n = 0; n < N; ++n) same = same && (a[n] == b[n]);
+    if (same) atomicOr(&flags[2], 1);
+}
+
+__global__ void __launch_bounds__(256) k_mode_key(const int32_t *__restrict__ idx, int N, int n, int64_t nnz,
+                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) {
+        keys[q] = (uint32_t)idx[q * N + n];
+        vals[q] = (uint32_t)q;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_hist(const uint32_t *__restrict__ keys, int64_t nnz,
+                                              uint32_t *__restrict__ counts)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) atomicAdd(&counts[keys[q]], 1u);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter(const uint32_t *__restrict__ rows, const uint32_t *__restrict__ ids,
+                                                 int64_t nnz, const int64_t *__restrict__ row_ptr,
+                                                 const RowPlace *__restrict__ place, const WaveInfo *__restrict__ waves,
+                                                 const int32_t *__restrict__ idx, int N, int mode,
+                                                 const double *__restrict__ val, OidxArg oidx, T *__restrict__ xval,
+                                                 int32_t *__restrict__ perm)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const uint32_t r = rows[p];
+    const uint32_t e = ids[p];
+    const int64_t q = p - row_ptr[r];
+    const RowPlace P = place[r];
+    int64_t slot;
+    if (P.glog >= 0) {
+        const int64_t g = 1ll << P.glog;
+        slot = P.base + (q >> P.glog) * kWave + ((int64_t)P.sub << P.glog) + (q & (g - 1));
+    } else {
+        slot = waves[P.base + q / kChunk].base + (q % kChunk);
+    }
+    int m = 0;
+    for (int k = 0; k < N; ++k) {
+        if (k == mode) continue;
+        oidx.p[m][slot] = idx[(int64_t)e * N + k];
+        ++m;
+    }
+    xval[slot] = (T)val[e];
+    perm[slot] = (int32_t)e;
+}
+
+__global__ void __launch_bounds__(256) k_invperm(const int32_t *__restrict__ perm, int64_t nslots,
+                                                 int32_t *__restrict__ pos)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nslots && perm[s] >= 0) pos[perm[s]] = (int32_t)s;
+}
+
+__global__ void __launch_bounds__(256) k_eslot(const int32_t *__restrict__ perm, int64_t nslots,
+                                               const int32_t *__restrict__ pos, int32_t *__restrict__ eslot)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nslots) eslot[s] = perm[s] >= 0 ? pos[perm[s]] : -1;
+}
+
+static int bits_for(int64_t v)
+{
+    int b = 1;
+    while (b < 32 && (int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+#define CHECK_HIP(x)                         \
+    do {                                     \
+        hipError_t e_ = (x);                 \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+
+// Host part of the row-group plan of one mode (see internal.h).
+struct HostPlan {
+    std::vector<WaveInfo> waves;
+    std::vector<int32_t> row_order;
+    std::vector<RowPlace> place;
+    std::vector<LongRow> longrows;
+    std::vector<int64_t> row_ptr;
+    int64_t nslots = 0, maxlen = 0;
+    int32_t nchunks = 0;
+};
+
+static void plan_mode(const std::vector<uint32_t> &cnt, HostPlan &hp)
+{
+    const int64_t I = (int64_t)cnt.size();
+    std::vector<int32_t> cls[7], longs;
+    for (int64_t r = 0; r < I; ++r) {
+        const int64_t len = cnt[r];
+        hp.maxlen = std::max<int64_t>(hp.maxlen, len);
+        if (len > kChunk) {
+            longs.push_back((int32_t)r);
+            continue;
+        }
+        int c = 0;
+        while (((len + (int64_t(1) << c) - 1) >> c) > kLaneTarget) ++c;
+        cls[c].push_back((int32_t)r);
+    }
+    auto by_len = [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; };
+    for (auto &v : cls) std::stable_sort(v.begin(), v.end(), by_len);
+    std::stable_sort(longs.begin(), longs.end(), by_len);
+
+    hp.place.assign(I, RowPlace{0, 0, 0});
+    hp.row_order.clear();
+    hp.waves.clear();
+    hp.longrows.clear();
+    int64_t slot = 0;
+    for (int c = 0; c < 7; ++c) {
+        const int per = kWave >> c;
+        const std::vector<int32_t> &v = cls[c];
+        for (size_t i = 0; i < v.size(); i += per) {
+            const int nrows = (int)std::min<size_t>(per, v.size() - i);
+            const int64_t lmax = cnt[v[i]];
+            const int32_t K = (int32_t)((lmax + (int64_t(1) << c) - 1) >> c);
+            WaveInfo w{};
+            w.base = slot;
+            w.K = K;
+            w.glog = c;
+            w.first = (int32_t)hp.row_order.size();
+            w.nrows = nrows;
+            w.chunk = -1;
+            for (int j = 0; j < nrows; ++j) {
+                hp.place[v[i + j]] = RowPlace{slot, c, j};
+                hp.row_order.push_back(v[i + j]);
+            }
+            hp.waves.push_back(w);
+            slot += (int64_t)kWave * K;
+        }
+    }
+    for (int32_t r : longs) {
+        const int64_t len = cnt[r];
+        const int32_t nch = (int32_t)((len + kChunk - 1) / kChunk);
+        hp.place[r] = RowPlace{(int64_t)hp.waves.size(), -1, 0};
+        hp.longrows.push_back(LongRow{r, hp.nchunks, nch, 0});
+        const int32_t pos = (int32_t)hp.row_order.size();
+        hp.row_order.push_back(r);
+        for (int32_t ch = 0; ch < nch; ++ch) {
+            const int64_t n = std::min<int64_t>(kChunk, len - (int64_t)ch * kChunk);
+            WaveInfo w{};
+            w.base = slot;
+            w.K = (int32_t)((n + kWave - 1) / kWave);
+            w.glog = 6;
+            w.first = pos;
+            w.nrows = 1;
+            w.chunk = hp.nchunks++;
+            hp.waves.push_back(w);
+            slot += (int64_t)kWave * w.K;
+        }
+    }
+    hp.nslots = slot;
+    hp.row_ptr.assign(I + 1, 0);
+    for (int64_t r = 0; r < I; ++r) hp.row_ptr[r + 1] = hp.row_ptr[r] + cnt[r];
+}
+
+hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, char *scratch, size_t scratch_bytes,
+                         int *bad)
+{
+    *bad = 0;
+    const int N = c->N;
+    const int64_t nnz = c->d.nnz;
+    hipStream_t st = c->stream;
+    int64_t Imax = 0;
+    for (int n = 0; n < N; ++n) Imax = std::max<int64_t>(Imax, c->d.dims[n]);
+
+    Bump b{scratch, 0, scratch_bytes};
+    auto *ka = (uint32_t *)b.take(nnz * 4), *kb = (uint32_t *)b.take(nnz * 4);
+    auto *va = (uint32_t *)b.take(nnz * 4), *vb = (uint32_t *)b.take(nnz * 4);
+    auto *counts = (uint32_t *)b.take(Imax * 4);
+    auto *place = (RowPlace *)b.take(Imax * sizeof(RowPlace));
+    auto *rptr = (int64_t *)b.take((Imax + 1) * 8);
+    auto *pos = (int32_t *)b.take(nnz * 4);
+    if (!ka || !kb || !va || !vb || !counts || !place || !rptr || !pos) return hipErrorOutOfMemory;
+
+    // 1. bounds and finiteness
+    DimsArg dm{};
+    dm.N = N;
+    for (int n = 0; n < N; ++n) dm.d[n] = c->d.dims[n];
+    CHECK_HIP(hipMemsetAsync(c->flags, 0, 64, st));
+    hipLaunchKernelGGL(k_validate, dim3(std::min<int64_t>(grid_for(nnz), 4096)), dim3(256), 0, st, idx, val, nnz, dm,
+                       c->flags);
+    int32_t fl[16] = {};
+    CHECK_HIP(hipMemcpyAsync(fl, c->flags, 64, hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    if (fl[0]) { *bad = 1; return hipSuccess; }
+    if (fl[1]) { *bad = 2; return hipSuccess; }
+
+    // 2. duplicates: lexicographic order by stable LSD passes, last mode first
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), dim3(256), 0, st, va, nnz);
+    for (int n = N - 1; n >= 0; --n) {
+        hipLaunchKernelGGL(k_gather_key, dim3(grid_for(nnz)), dim3(256), 0, st, idx, N, n, va, nnz, ka);
+        size_t tb = c->sort_tmp_bytes;
+        CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, tb, ka, kb, va, vb, (int)nnz, 0,
+                                                     bits_for(c->d.dims[n]), st));
+        std::swap(va, vb);
+    }
+    hipLaunchKernelGGL(k_dupcheck, dim3(grid_for(nnz)), dim3(256), 0, st, idx, N, va, nnz, c->flags);
+    CHECK_HIP(hipMemcpyAsync(fl, c->flags, 64, hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    if (fl[2]) { *bad = 3; return hipSuccess; }
+
+    // 3. per-mode layouts
+    std::vector<uint32_t> cnt;
+    for (int n = 0; n < N; ++n) {
+        const int64_t I = c->d.dims[n];
+        ModeLayout &L = c->lay[n];
+        hipLaunchKernelGGL(k_mode_key, dim3(grid_for(nnz)), dim3(256), 0, st, idx, N, n, nnz, ka, va);
+        size_t tb = c->sort_tmp_bytes;
+        CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, tb, ka, kb, va, vb, (int)nnz, 0, bits_for(I), st));
+        CHECK_HIP(hipMemsetAsync(counts, 0, I * 4, st));
+        hipLaunchKernelGGL(k_hist, dim3(grid_for(nnz)), dim3(256), 0, st, kb, nnz, counts);
+        cnt.assign(I, 0);
+        CHECK_HIP(hipMemcpyAsync(cnt.data(), counts, I * 4, hipMemcpyDeviceToHost, st));
+        CHECK_HIP(hipStreamSynchronize(st));
+
+        HostPlan hp;
+        plan_mode(cnt, hp);
+        if (hp.nslots > c->lay[n].nslots || (int64_t)hp.waves.size() > L.nwaves ||
+            (int64_t)hp.longrows.size() > L.nlong || hp.nchunks > L.nchunks) {
+            // capacities were stored in the layout by the carve step
+            return hipErrorOutOfMemory;
+        }
+        L.nslots = hp.nslots;
+        L.npad = hp.nslots - nnz;
+        L.nwaves = (int32_t)hp.waves.size();
+        L.nlong = (int32_t)hp.longrows.size();
+        L.nchunks = hp.nchunks;
+        L.maxlen = hp.maxlen;
+        CHECK_HIP(hipMemcpyAsync(L.waves, hp.waves.data(), hp.waves.size() * sizeof(WaveInfo),
+                                 hipMemcpyHostToDevice, st));
+        CHECK_HIP(hipMemcpyAsync(L.row_order, hp.row_order.data(), hp.row_order.size() * 4, hipMemcpyHostToDevice,
+                                 st));
+        if (!hp.longrows.empty())
+            CHECK_HIP(hipMemcpyAsync(L.longrows, hp.longrows.data(), hp.longrows.size() * sizeof(LongRow),
+                                     hipMemcpyHostToDevice, st));
+        CHECK_HIP(hipMemcpyAsync(place, hp.place.data(), I * sizeof(RowPlace), hipMemcpyHostToDevice, st));
+        CHECK_HIP(hipMemcpyAsync(rptr, hp.row_ptr.data(), (I + 1) * 8, hipMemcpyHostToDevice, st));
+
+        const int64_t ns = hp.nslots;
+        CHECK_HIP(hipMemsetAsync(L.oidx[0], 0xff, ns * 4, st));
+        for (int m = 1; m < N - 1; ++m) CHECK_HIP(hipMemsetAsync(L.oidx[m], 0, ns * 4, st));
+        CHECK_HIP(hipMemsetAsync(L.xval, 0, ns * c->tsize, st));
+        CHECK_HIP(hipMemsetAsync(L.perm, 0xff, ns * 4, st));
+        OidxArg oa{};
+        for (int m = 0; m < N - 1; ++m) oa.p[m] = L.oidx[m];
+        if (c->d.precision == VEST_FP32)
+            hipLaunchKernelGGL(k_scatter<float>, dim3(grid_for(nnz)), dim3(256), 0, st, kb, vb, nnz, rptr, place,
+                               L.waves, idx, N, n, val, oa, reinterpret_cast<float *>(L.xval), L.perm);
+        else
+            hipLaunchKernelGGL(k_scatter<double>, dim3(grid_for(nnz)), dim3(256), 0, st, kb, vb, nnz, rptr, place,
+                               L.waves, idx, N, n, val, oa, reinterpret_cast<double *>(L.xval), L.perm);
+        CHECK_HIP(hipGetLastError());
+        // the host vectors above are read by pending copies: wait before reuse
+        CHECK_HIP(hipStreamSynchronize(st));
+    }
+
+    // 4. slot of every entry in the core layout (mode N-1)
+    const ModeLayout &C = c->lay[N - 1];
+    hipLaunchKernelGGL(k_invperm, dim3(grid_for(C.nslots)), dim3(256), 0, st, C.perm, C.nslots, pos);
+    for (int n = 0; n < N - 1; ++n) {
+        const ModeLayout &L = c->lay[n];
+        hipLaunchKernelGGL(k_eslot, dim3(grid_for(L.nslots)), dim3(256), 0, st, L.perm, L.nslots, pos, L.eslot);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vest

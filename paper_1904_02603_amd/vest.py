@@ -1,0 +1,222 @@
+"""ctypes binding of the libvest C ABI (include/vest.h).
+
+Argument marshalling only: every step runs in the HIP kernels of libvest.so.
+Device memory and streams come from PyTorch.  The library must be built
+(``python -m paper_1904_02603_amd.build``); importing this module on a
+machine where it is missing raises immediately -- there is no fallback.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvest.so")
+MAX_ORDER = 10
+
+OK, EINVAL, ENOSPC, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+REG_LF, REG_L1 = 0, 1
+FP64, FP32 = 0, 1
+
+EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
+           "vest_responsibility", "vest_prune", "vest_loss", "vest_layout_stats",
+           "vest_destroy", "vest_strerror", "vest_last_error"]
+
+
+class VestError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+class Desc(C.Structure):
+    _fields_ = [
+        ("order", C.c_int32),
+        ("reg", C.c_int32),
+        ("precision", C.c_int32),
+        ("reserved", C.c_int32),
+        ("lam", C.c_double),
+        ("nnz", C.c_int64),
+        ("dims", C.c_int64 * MAX_ORDER),
+        ("ranks", C.c_int32 * MAX_ORDER),
+    ]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libvest.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libvest.so is not built (%s); run python -m paper_1904_02603_amd.build" % path)
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    PD = C.POINTER(Desc)
+    lib.vest_workspace_bytes.argtypes = [PD, C.POINTER(C.c_size_t)]
+    lib.vest_init.argtypes = [PD, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(vp)]
+    lib.vest_sweep_factor.argtypes = [vp, i32]
+    lib.vest_sweep_core.argtypes = [vp]
+    lib.vest_responsibility.argtypes = [vp, vp, vp]
+    lib.vest_prune.argtypes = [vp, i64, vp]
+    lib.vest_loss.argtypes = [vp, vp]
+    lib.vest_layout_stats.argtypes = [vp, i32, vp]
+    lib.vest_destroy.argtypes = [vp]
+    lib.vest_strerror.argtypes = [C.c_int]
+    lib.vest_strerror.restype = C.c_char_p
+    lib.vest_last_error.argtypes = []
+    lib.vest_last_error.restype = C.c_char_p
+    for name in ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
+                 "vest_responsibility", "vest_prune", "vest_loss", "vest_layout_stats", "vest_destroy"]:
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc, where):
+    if rc != OK:
+        msg = _lib.vest_last_error().decode(errors="replace")
+        raise VestError(rc, where, msg)
+
+
+def make_desc(dims, ranks, nnz, reg=REG_LF, lam=0.01, precision=FP64):
+    d = Desc()
+    d.order = len(dims)
+    d.reg = reg
+    d.precision = precision
+    d.reserved = 0
+    d.lam = lam
+    d.nnz = nnz
+    for n in range(len(dims)):
+        d.dims[n] = int(dims[n])
+        d.ranks[n] = int(ranks[n])
+    return d
+
+
+def workspace_bytes(dims, ranks, nnz, reg=REG_LF, lam=0.01, precision=FP64):
+    lib = load_library()
+    d = make_desc(dims, ranks, nnz, reg, lam, precision)
+    out = C.c_size_t(0)
+    _check(lib.vest_workspace_bytes(C.byref(d), C.byref(out)), "vest_workspace_bytes")
+    return int(out.value)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _ptr_array(ts):
+    return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def masks_to_bool(fmask, J):
+    """int32 bit masks [I] -> bool [I, J]."""
+    bits = torch.arange(J, device=fmask.device, dtype=torch.int32)
+    return ((fmask.unsqueeze(1) >> bits) & 1).bool()
+
+
+def bool_to_masks(mask_bool):
+    """bool [I, J] -> int32 bit masks [I] (J <= 31)."""
+    J = mask_bool.shape[1]
+    w = (torch.ones(J, dtype=torch.int64, device=mask_bool.device) << torch.arange(J, device=mask_bool.device))
+    return (mask_bool.to(torch.int64) * w).sum(dim=1).to(torch.int32)
+
+
+class VestContext:
+    """One factorisation job: device-resident state plus its libvest context.
+
+    factors / core / masks are torch CUDA tensors owned by this object and
+    updated in place by the library (factors float64 [I_n, J], core float64
+    with shape (J,)*N, factor masks int32 [I_n] bit masks, core mask uint8).
+    """
+
+    def __init__(self, idx, val, factors, core, reg=REG_LF, lam=0.01, precision=FP64,
+                 fmask=None, cmask=None, stream=None, device="cuda"):
+        self.lib = load_library()
+        dev = torch.device(device)
+        self.idx = torch.as_tensor(idx, dtype=torch.int32, device=dev).contiguous()
+        self.val = torch.as_tensor(val, dtype=torch.float64, device=dev).contiguous()
+        self.N = self.idx.shape[1]
+        self.factors = [torch.as_tensor(f, dtype=torch.float64, device=dev).clone().contiguous() for f in factors]
+        self.core = torch.as_tensor(core, dtype=torch.float64, device=dev).clone().contiguous()
+        self.dims = [int(f.shape[0]) for f in self.factors]
+        self.ranks = [int(f.shape[1]) for f in self.factors]
+        self.J = self.ranks[0]
+        self.fmask = ([torch.zeros(I, dtype=torch.int32, device=dev) for I in self.dims] if fmask is None
+                      else [torch.as_tensor(m, dtype=torch.int32, device=dev).clone().contiguous() for m in fmask])
+        self.cmask = (torch.zeros(self.core.shape, dtype=torch.uint8, device=dev) if cmask is None
+                      else torch.as_tensor(cmask, dtype=torch.uint8, device=dev).clone().contiguous())
+        self.reg, self.lam, self.precision = reg, lam, precision
+        self.nnz = int(self.idx.shape[0])
+        self.desc = make_desc(self.dims, self.ranks, self.nnz, reg, lam, precision)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        nb = C.c_size_t(0)
+        _check(self.lib.vest_workspace_bytes(C.byref(self.desc), C.byref(nb)), "vest_workspace_bytes")
+        self.ws_bytes = int(nb.value)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.ctx = C.c_void_p()
+        with torch.cuda.stream(self.stream):
+            rc = self.lib.vest_init(C.byref(self.desc), C.c_void_p(self.stream.cuda_stream),
+                                    _ptr(self.idx), _ptr(self.val), _ptr_array(self.factors),
+                                    _ptr(self.core), _ptr_array(self.fmask), _ptr(self.cmask),
+                                    C.c_void_p(self._ws_ptr), C.c_size_t(self.ws_bytes), C.byref(self.ctx))
+        _check(rc, "vest_init")
+        self.core_key = torch.empty(self.core.shape, dtype=torch.float64, device=dev)
+        self.factor_keys = [torch.empty_like(f) for f in self.factors]
+
+    # -- Alg. 4
+    def sweep_factor(self, mode):
+        _check(self.lib.vest_sweep_factor(self.ctx, int(mode)), "vest_sweep_factor")
+
+    # -- Eq. 12 / 14
+    def sweep_core(self):
+        _check(self.lib.vest_sweep_core(self.ctx), "vest_sweep_core")
+
+    # -- Eq. 5 / 6
+    def responsibility(self):
+        _check(self.lib.vest_responsibility(self.ctx, _ptr(self.core_key), _ptr_array(self.factor_keys)),
+               "vest_responsibility")
+        return self.core_key, self.factor_keys
+
+    # -- Sec. 3.3
+    def prune(self, core_k, factor_k):
+        arr = (C.c_int64 * self.N)(*[int(k) for k in factor_k])
+        _check(self.lib.vest_prune(self.ctx, int(core_k), arr), "vest_prune")
+
+    # -- Eq. 1 / 2 / 4
+    def loss(self):
+        out = (C.c_double * 5)()
+        _check(self.lib.vest_loss(self.ctx, out), "vest_loss")
+        return {"sse": out[0], "xnorm2": out[1], "reg": out[2], "loss": out[3], "re": out[4]}
+
+    def iteration(self):
+        for n in range(self.N):
+            self.sweep_factor(n)
+        self.sweep_core()
+
+    def layout_stats(self, mode):
+        out = (C.c_int64 * 8)()
+        _check(self.lib.vest_layout_stats(self.ctx, int(mode), out), "vest_layout_stats")
+        keys = ["slots", "pad", "waves", "long_rows", "long_chunks", "max_row", "rows", "nnz"]
+        return dict(zip(keys, list(out)))
+
+    def factor_masks_bool(self):
+        return [masks_to_bool(m, J) for m, J in zip(self.fmask, self.ranks)]
+
+    def marked_counts(self):
+        return [int(masks_to_bool(m, J).sum()) for m, J in zip(self.fmask, self.ranks)], int(self.cmask.sum())
+
+    def close(self):
+        if self.ctx is not None and self.ctx.value:
+            self.lib.vest_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
