@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 512 MiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -163,6 +165,12 @@ def main():
     vest.load_library()
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     log("generating workload %s ..." % args.workload)
     p = synth.workload(args.workload, nnz=args.nnz)

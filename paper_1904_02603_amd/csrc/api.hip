@@ -90,7 +90,7 @@ int plan_workspace(const vest_desc *d, Plan *p)
         return VEST_EDEVICE;
     }
     p->sort_tmp = (t1 > t2 ? t1 : t2) + 256;
-    p->scratch_bytes = (size_t)nnz * 4 * 5 + (size_t)Imax * (4 + 16 + 8) + 8 + 16 * 256;
+    p->scratch_bytes = (size_t)nnz * 4 * 4 + (size_t)Imax * (4 + 16 + 8) + 8 + 16 * 256;
     return VEST_OK;
 }
 
@@ -117,22 +117,29 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
         for (int m = 0; m < N - 1; ++m) L.oidx[m] = (int32_t *)take(sb * 4);
         L.xval = take(sb * ts);
         L.perm = (int32_t *)take(sb * 4);
-        L.eslot = n < N - 1 ? (int32_t *)take(sb * 4) : nullptr;
         L.longrows = (LongRow *)take(p.long_bound[n] * sizeof(LongRow));
     }
     c->e = take(p.slot_bound[N - 1] * ts);
+    c->ms = take((p.slot_bound[N - 1] + 63) / 64 * 64 * J * ts);
+    c->hdiag = (double *)take(c->G * 8);
     for (int n = 0; n < N; ++n) c->Gp[n] = take(c->G * ts);
     for (int n = 0; n < N; ++n)
         c->A32[n] = c->d.precision == VEST_FP32 ? (float *)take(c->d.dims[n] * J * 4) : nullptr;
     for (int m = 0; m + 2 < N; ++m) c->colA[m] = take(c->d.dims[m] * J * ts);
     const int gw = gram_width(J);
     const int64_t Il = c->d.dims[N - 1];
-    c->rowbuf = (double *)take(Il * gw * 8);
+    c->ldrb = rowbuf_width(N, J);
+    const int64_t gsq = (int64_t)gw * gw > (int64_t)keys_width(N, J) * round8(2 * J)
+                            ? (int64_t)gw * gw
+                            : (int64_t)keys_width(N, J) * round8(2 * J);
+    // (keys_width x round8(2J) also bounds the R-only batches: round8(J S) x round8(J))
+    c->rowbuf = (double *)take(Il * c->ldrb * 8);
     c->kp = (double *)take(Il * gw * 8);
-    c->gram_part = (double *)take(p.gram_chunks * gw * gw * 8);
-    c->gram = (double *)take(gw * gw * 8);
+    c->gram_part = (double *)take(p.gram_chunks * gsq * 8);
+    c->gram = (double *)take(gsq * 8);
     c->dprev = (double *)take(J * J * 8);
-    const int na = nacc_vc(J) > 2 * J ? nacc_vc(J) : 2 * J;
+    int na = nacc_vc(J) > 2 * J ? nacc_vc(J) : 2 * J;
+    na = na > keys_nacc(N, J) ? na : keys_nacc(N, J);
     c->partials = (double *)take(p.chunk_bound * na * 8);
     c->red = (double *)take((16 * kLossBlocks + 64) * 8);
     c->flags = (int32_t *)take(64);
@@ -195,13 +202,14 @@ static int ensure_a32(vest_ctx *c)
 
 static int ensure_residual(vest_ctx *c)
 {
-    if (c->e_valid) return VEST_OK;
+    if (c->e_valid && c->ms_valid) return VEST_OK;
     int rc = ensure_a32(c);
     if (rc) return rc;
     rc = ensure_gp(c, c->N - 1);
     if (rc) return rc;
     CALL_HIP(c, launch_rowgroup(c, c->N - 1, OP_RESID), "residual");
     c->e_valid = true;
+    c->ms_valid = true;
     return VEST_OK;
 }
 
@@ -319,7 +327,7 @@ int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const dou
     he = hipMemsetAsync(cnt, 0, (c->N + 1) * 8, c->stream);
     if (he == hipSuccess) he = launch_mask_init(c, cnt);
     if (he == hipSuccess) he = hipMemcpyAsync(hc, cnt, (c->N + 1) * 8, hipMemcpyDeviceToHost, c->stream);
-    if (he == hipSuccess) he = hipMemsetAsync(c->rowbuf, 0, c->d.dims[c->N - 1] * gram_width(c->J) * 8, c->stream);
+    if (he == hipSuccess) he = hipMemsetAsync(c->rowbuf, 0, c->d.dims[c->N - 1] * c->ldrb * 8, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) { int r = device_error(nullptr, he, "masks"); delete c; return r; }
     for (int n = 0; n < c->N; ++n) c->marked_fac[n] = hc[n];
@@ -340,6 +348,8 @@ int vest_sweep_factor(vest_ctx *c, int32_t mode)
     if ((rc = ensure_gp(c, mode))) return rc;
     CALL_HIP(c, launch_rowgroup(c, mode, OP_SWEEP), "factor sweep");
     c->e_valid = false;
+    c->ms_valid = false;
+    c->hdiag_valid = false;
     return VEST_OK;
 }
 
@@ -351,6 +361,7 @@ int vest_sweep_core(vest_ctx *c)
     CALL_HIP(c, launch_core_sweep(c), "core sweep");
     c->core_version++;
     c->e_valid = true;
+    c->hdiag_valid = true;
     return refresh_gp(c);
 }
 
@@ -395,6 +406,8 @@ int vest_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
             CALL_HIP(c, launch_prune(c, n, factor_k[n]), "prune factor");
             c->marked_fac[n] += factor_k[n];
             c->a32_valid[n] = false;
+            c->ms_valid = false;
+            c->hdiag_valid = false;
         }
     c->e_valid = false;
     c->keys_pending = false;

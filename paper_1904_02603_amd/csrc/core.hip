@@ -41,19 +41,31 @@ struct SlabArgs {
     int64_t dimA[NL];
     int32_t lead[NL];             // leading core indices of this slab
     int32_t lprev[NL];            // ... of the previous slab
-    const T *Amid;                // mode N-2 factor, row-major
+    const T *ms;                  // mode N-2 factor row of every slot (see ms_index)
     const T *Alast;               // mode N-1 factor, row-major
     T *e;
     const double *dprev;          // [J][J] change of the previous slab's elements
-    double *rowbuf;               // [I_{N-1}][gw]
-    int32_t gw;
+    double *rowbuf;               // [I_{N-1}][ldrb]
+    int32_t ldrb;
     double *partials;
+    int32_t blead[kKeyAcc * NL];  // k_slabkeys: leading indices of each slab of the batch
 };
+
+// The mode N-2 factor row of every entry is read from the slot-ordered copy
+// written by the residual pass (coalesced, no gather).  Entries are taken U
+// at a time per lane and every load of a batch is issued unconditionally (the
+// slot is clamped into the wave's range), so a batch costs two memory
+// latencies -- streamed loads, then the column gathers of the leading factors
+// -- instead of a dependent chain per entry; padding slots are masked out of
+// the arithmetic by selects.
+constexpr int kSlabU = 2;
 
 template <int N, int J, typename T, bool ACC>
 __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 {
     constexpr int NA = nacc_vc(J);
+    constexpr int U = kSlabU;
+    constexpr int NI = N > 2 ? N - 2 : 1;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (wave >= a.nwaves) return;
@@ -81,38 +93,58 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
-    for (int k = 0; k < wi.K; ++k) {
-        const int64_t sl = wi.base + (int64_t)k * kWave + lane;
-        int32_t ii[N - 1];
-        ii[0] = a.oidx[0][sl];
-        if (ii[0] < 0) continue;
+    for (int k0 = 0; k0 < wi.K; k0 += U) {
+        int64_t sl[U];
+        int32_t ii[U][NI];
+        T mv[U][J], ev[U];
 #pragma unroll
-        for (int m = 1; m < N - 1; ++m) ii[m] = a.oidx[m][sl];
-        T mv[J];
-        load_row<J, T>(a.Amid + (int64_t)ii[N - 2] * J, mv);
-        T ev = a.e[sl];
-        if (a.has_prev) {
-            T pp = T(1);
+        for (int q = 0; q < U; ++q) {
+            const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
+            sl[q] = wi.base + (int64_t)kk * kWave + lane;
 #pragma unroll
-            for (int m = 0; m < N - 2; ++m) pp *= a.colA[m][(int64_t)a.lprev[m] * a.dimA[m] + ii[m]];
-            T du = mv[0] * u[0];
+            for (int m = 0; m < NI; ++m) ii[q][m] = a.oidx[m][sl[q]];
+            ev[q] = a.e[sl[q]];
 #pragma unroll
-            for (int t = 1; t < J; ++t) du = vfma(mv[t], u[t], du);
-            ev -= pp * du;
-            a.e[sl] = ev;
+            for (int t = 0; t < J; ++t) mv[q][t] = a.ms[ms_index<J>(sl[q], t)];
         }
-        if constexpr (ACC) {
-            T p = T(1);
+        bool ok[U];
+        T p[U], pp[U];
 #pragma unroll
-            for (int m = 0; m < N - 2; ++m) p *= a.colA[m][(int64_t)a.lead[m] * a.dimA[m] + ii[m]];
-            T w[J];
+        for (int q = 0; q < U; ++q) {
+            ok[q] = (k0 + q < wi.K) && ii[q][0] >= 0;
+            T pv = T(1), pr = T(1);
 #pragma unroll
-            for (int t = 0; t < J; ++t) w[t] = p * mv[t];
+            for (int m = 0; m < N - 2; ++m) {
+                const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
+                if constexpr (ACC) pv *= a.colA[m][(int64_t)a.lead[m] * a.dimA[m] + i];
+                if (a.has_prev) pr *= a.colA[m][(int64_t)a.lprev[m] * a.dimA[m] + i];
+            }
+            p[q] = ok[q] ? pv : T(0);
+            pp[q] = ok[q] ? pr : T(0);
+            ev[q] = ok[q] ? ev[q] : T(0);
 #pragma unroll
-            for (int t = 0; t < J; ++t) {
-                s[t] = vfma(ev, w[t], s[t]);
+            for (int t = 0; t < J; ++t) mv[q][t] = ok[q] ? mv[q][t] : T(0);
+        }
 #pragma unroll
-                for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(w[t], w[v], s[J + sym<J>(t, v)]);
+        for (int q = 0; q < U; ++q) {
+            T e = ev[q];
+            if (a.has_prev) {
+                T du = mv[q][0] * u[0];
+#pragma unroll
+                for (int t = 1; t < J; ++t) du = vfma(mv[q][t], u[t], du);
+                e -= pp[q] * du;
+                if (ok[q]) a.e[sl[q]] = e;
+            }
+            if constexpr (ACC) {
+                T w[J];
+#pragma unroll
+                for (int t = 0; t < J; ++t) w[t] = p[q] * mv[q][t];
+#pragma unroll
+                for (int t = 0; t < J; ++t) {
+                    s[t] = vfma(e, w[t], s[t]);
+#pragma unroll
+                    for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(w[t], w[v], s[J + sym<J>(t, v)]);
+                }
             }
         }
     }
@@ -123,22 +155,97 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
             return;
         }
         if (has_row && (lane & ((1 << wi.glog) - 1)) == 0) {
-            double *dst = a.rowbuf + (int64_t)row * a.gw;
+            double *dst = a.rowbuf + (int64_t)row * a.ldrb;
 #pragma unroll
             for (int v = 0; v < NA; ++v) dst[v] = (double)s[v];
         }
     }
 }
 
-template <int J>
-__global__ void __launch_bounds__(64) k_slab_long(const double *__restrict__ part, const LongRow *__restrict__ lr,
-                                                  double *__restrict__ rowbuf, int gw)
+// Core responsibility statistics of SB consecutive slabs in one pass:
+// per row r and slab b,  R_b[t] = sum e p_b a^(N-1)_t  and, when WITH_D,
+// D_b[t] = sum (p_b a^(N-1)_t)^2.  The residual is not modified.  Loads as in
+// k_slab.
+template <int N, int J, typename T, int SB, bool WITH_D>
+__global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
 {
-    constexpr int NA = nacc_vc(J);
+    constexpr int PER = WITH_D ? 2 * J : J;
+    constexpr int NA = PER * SB;
+    constexpr int U = 2;
+    constexpr int NL = SlabArgs<N, J, T>::NL;
+    constexpr int NI = N > 2 ? N - 2 : 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (wave >= a.nwaves) return;
+    const WaveInfo wi = a.waves[wave];
+    const int grp = lane >> wi.glog;
+    const bool has_row = grp < wi.nrows;
+    const int row = has_row ? a.row_order[wi.first + grp] : 0;
+    T s[NA];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) s[v] = T(0);
+    for (int k0 = 0; k0 < wi.K; k0 += U) {
+        int64_t sl[U];
+        int32_t ii[U][NI];
+        T mv[U][J], ev[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
+            sl[q] = wi.base + (int64_t)kk * kWave + lane;
+#pragma unroll
+            for (int m = 0; m < NI; ++m) ii[q][m] = a.oidx[m][sl[q]];
+            ev[q] = a.e[sl[q]];
+#pragma unroll
+            for (int t = 0; t < J; ++t) mv[q][t] = a.ms[ms_index<J>(sl[q], t)];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const bool ok = (k0 + q < wi.K) && ii[q][0] >= 0;
+            const T evq = ok ? ev[q] : T(0);
+            T mq[J];
+#pragma unroll
+            for (int t = 0; t < J; ++t) mq[t] = ok ? mv[q][t] : T(0);
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                if (b >= nsb) break;
+                T p = T(1);
+#pragma unroll
+                for (int m = 0; m < N - 2; ++m) {
+                    const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
+                    p *= a.colA[m][(int64_t)a.blead[b * NL + m] * a.dimA[m] + i];
+                }
+                const T ep = evq * p;
+#pragma unroll
+                for (int t = 0; t < J; ++t) {
+                    s[b * PER + t] = vfma(ep, mq[t], s[b * PER + t]);
+                    if constexpr (WITH_D) {
+                        const T w = p * mq[t];
+                        s[b * PER + J + t] = vfma(w, w, s[b * PER + J + t]);
+                    }
+                }
+            }
+        }
+    }
+    group_reduce<NA, T>(s, wi.glog);
+    if (wi.chunk >= 0) {
+        store_partial<NA, T>(a.partials, wi.chunk, s, lane);
+        return;
+    }
+    if (has_row && (lane & ((1 << wi.glog) - 1)) == 0) {
+        double *dst = a.rowbuf + (int64_t)row * a.ldrb;
+#pragma unroll
+        for (int v = 0; v < NA; ++v) dst[v] = (double)s[v];
+    }
+}
+
+template <int NA>
+__global__ void __launch_bounds__(64) k_slab_long(const double *__restrict__ part, const LongRow *__restrict__ lr,
+                                                  double *__restrict__ rowbuf, int ldrb)
+{
     __shared__ double sh[NA];
     const LongRow L = lr[blockIdx.x];
     sum_partials<NA>(part, L, sh, threadIdx.x);
-    for (int v = threadIdx.x; v < NA; v += 64) rowbuf[(int64_t)L.row * gw + v] = sh[v];
+    for (int v = threadIdx.x; v < NA; v += 64) rowbuf[(int64_t)L.row * ldrb + v] = sh[v];
 }
 
 // kp row r = [a_r (J) | packed a_r a_r^T (J(J+1)/2) | 0 padding]
@@ -159,6 +266,23 @@ __global__ void __launch_bounds__(256) k_kp(const double *__restrict__ A, int64_
     for (int v = nacc_vc(J); v < gw; ++v) d[v] = 0.0;
 }
 
+// kp2 row r = [a_r (J) | a_r^2 (J) | 0 padding]
+template <int J>
+__global__ void __launch_bounds__(256) k_kp2(const double *__restrict__ A, int64_t I, int w, double *__restrict__ kp)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= I) return;
+    double a[J];
+    load_row<J, double>(A + r * J, a);
+    double *d = kp + r * w;
+#pragma unroll
+    for (int t = 0; t < J; ++t) {
+        d[t] = a[t];
+        d[J + t] = a[t] * a[t];
+    }
+    for (int v = 2 * J; v < w; ++v) d[v] = 0.0;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, int64_t I, int J, T *__restrict__ out)
 {
@@ -168,21 +292,22 @@ __global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, i
     out[q] = (T)A[i * J + j];
 }
 
-// Partial Gram of kGramRows rows: part[b] = sum_r rowbuf_r^T kp_r (gw x gw).
+// Partial product of kGramRows rows: part[b] = sum_r rb_r^T kp_r (W1 x W2).
 // Thread (ti, tj) owns an 8 x 8 tile; rows are staged through LDS.
-template <int GW>
-__global__ void __launch_bounds__(256) k_gram(const double *__restrict__ rb, const double *__restrict__ kp,
-                                              int64_t nrows, double *__restrict__ part)
+template <int W1, int W2>
+__global__ void __launch_bounds__(256) k_gram(const double *__restrict__ rb, int ldrb, const double *__restrict__ kp,
+                                              int ldkp, int64_t nrows, double *__restrict__ part)
 {
-    constexpr int TB = GW / 8;
-    constexpr int NT = TB * TB;
+    constexpr int T1 = W1 / 8, T2 = W2 / 8;
+    constexpr int NT = T1 * T2;
+    static_assert(NT <= 256, "gram tile count");
     constexpr int BR = 16;
-    __shared__ double sx[BR][GW];
-    __shared__ double sy[BR][GW];
+    __shared__ double sx[BR][W1];
+    __shared__ double sy[BR][W2];
     const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
     const int64_t r1 = r0 + kGramRows < nrows ? r0 + kGramRows : nrows;
     const int t = threadIdx.x;
-    const int ti = t / TB, tj = t % TB;
+    const int ti = t / T2, tj = t % T2;
     double acc[8][8];
 #pragma unroll
     for (int p = 0; p < 8; ++p)
@@ -190,11 +315,28 @@ __global__ void __launch_bounds__(256) k_gram(const double *__restrict__ rb, con
         for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
     for (int64_t b0 = r0; b0 < r1; b0 += BR) {
         const int nb = (int)(r1 - b0 < BR ? r1 - b0 : BR);
+        constexpr int NX = (BR * W1 + 255) / 256, NY = (BR * W2 + 255) / 256;
+        double vx[NX], vy[NY];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            const int q = t + i * 256, rr = q / W1, cc = q % W1;
+            vx[i] = (q < BR * W1 && rr < nb) ? rb[(b0 + rr) * ldrb + cc] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NY; ++i) {
+            const int q = t + i * 256, rr = q / W2, cc = q % W2;
+            vy[i] = (q < BR * W2 && rr < nb) ? kp[(b0 + rr) * ldkp + cc] : 0.0;
+        }
         __syncthreads();
-        for (int q = t; q < BR * GW; q += blockDim.x) {
-            const int rr = q / GW, cc = q % GW;
-            sx[rr][cc] = rr < nb ? rb[(b0 + rr) * GW + cc] : 0.0;
-            sy[rr][cc] = rr < nb ? kp[(b0 + rr) * GW + cc] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            const int q = t + i * 256;
+            if (q < BR * W1) sx[q / W1][q % W1] = vx[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NY; ++i) {
+            const int q = t + i * 256;
+            if (q < BR * W2) sy[q / W2][q % W2] = vy[i];
         }
         __syncthreads();
         if (t < NT) {
@@ -213,30 +355,39 @@ __global__ void __launch_bounds__(256) k_gram(const double *__restrict__ rb, con
         }
     }
     if (t < NT) {
-        double *o = part + (int64_t)blockIdx.x * GW * GW;
+        double *o = part + (int64_t)blockIdx.x * W1 * W2;
 #pragma unroll
         for (int p = 0; p < 8; ++p)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) o[(ti * 8 + p) * GW + tj * 8 + q] = acc[p][q];
+            for (int q = 0; q < 8; ++q) o[(ti * 8 + p) * W2 + tj * 8 + q] = acc[p][q];
     }
 }
 
-// Fixed-order sum of the gram partials.
-__global__ void __launch_bounds__(256) k_gramsum(const double *__restrict__ part, int64_t nparts, int n,
-                                                 double *__restrict__ out)
+// Fixed-order sum of the gram partials: block b owns outputs 64 b .. 64 b + 63;
+// wave w of the block sums partials w, w + 16, ... (coalesced across lanes),
+// then the 16 wave sums are added in wave order.
+__global__ void __launch_bounds__(1024) k_gramsum(const double *__restrict__ part, int64_t nparts, int n,
+                                                  double *__restrict__ out)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int64_t c = 0;
-    for (; c + 4 <= nparts; c += 4) {
-        s0 += part[c * n + q];
-        s1 += part[(c + 1) * n + q];
-        s2 += part[(c + 2) * n + q];
-        s3 += part[(c + 3) * n + q];
+    __shared__ double sh[16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = blockIdx.x * 64 + lane;
+    double s0 = 0.0, s1 = 0.0;
+    if (q < n) {
+        int64_t c = w;
+        for (; c + 16 < nparts; c += 32) {
+            s0 += part[c * n + q];
+            s1 += part[(c + 16) * n + q];
+        }
+        if (c < nparts) s0 += part[c * n + q];
     }
-    for (; c < nparts; ++c) s0 += part[c * n + q];
-    out[q] = (s0 + s1) + (s2 + s3);
+    sh[w][lane] = s0 + s1;
+    __syncthreads();
+    if (w == 0 && q < n) {
+        double t = 0.0;
+        for (int i = 0; i < 16; ++i) t += sh[i][lane];
+        out[q] = t;
+    }
 }
 
 __device__ __forceinline__ int symr(int J, int t, int u)
@@ -249,61 +400,168 @@ __device__ __forceinline__ int symr(int J, int t, int u)
     return t * J - t * (t - 1) / 2 + (u - t);
 }
 
-// Sequential updates of one slab (KEYS = false) or its core keys (KEYS = true).
-template <int J, bool KEYS>
-__global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gram, double *core,
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sequential updates of one slab's unpruned elements in flat order, one
+// wave.  Lane l holds, for the elements q = l, l + 64, ..., the core value,
+// rr_q, H_qq, the reciprocal of the denominator and the running correction
+// sum_{p<q} H_qp D_p; the sequential chain reads them with readlane (no LDS
+// round trip) and only the correction update touches LDS, where H lives.  The
+// diagonal of H is kept (it is sum w_q^2, reused by the core keys).
+template <int J>
+__global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gram, double *__restrict__ core,
                                                   const uint8_t *__restrict__ cmask, int64_t base, double lambda,
-                                                  int reg, double *__restrict__ dprev, double *__restrict__ keys)
+                                                  int reg, double *__restrict__ dprev, double *__restrict__ hdiag)
 {
     constexpr int GW = gram_width(J);
     constexpr int B = J * J;
     constexpr int CPL = (B + kWave - 1) / kWave;
     __shared__ double sg[GW * GW];
     const int lane = threadIdx.x;
-    for (int q = lane; q < GW * GW; q += kWave) sg[q] = gram[q];
+    {
+        // all loads in flight before the LDS stores
+        constexpr int NL = (GW * GW + kWave - 1) / kWave;
+        double v[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int q = lane + i * kWave;
+            v[i] = q < GW * GW ? gram[q] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int q = lane + i * kWave;
+            if (q < GW * GW) sg[q] = v[i];
+        }
+    }
     __syncthreads();
     auto H = [&](int q, int q2) {
         return sg[(J + symr(J, q / J, q2 / J)) * GW + J + symr(J, q % J, q2 % J)];
     };
-    auto RR = [&](int q) { return sg[(q / J) * GW + (q % J)]; };
+    double gv[CPL], rv[CPL], hv[CPL], iv[CPL], corr[CPL], dv[CPL];
+    uint64_t mbits[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = lane + c * kWave;
+        const bool in = q < B;
+        const double h = in ? H(q, q) : 0.0;
+        gv[c] = in ? core[base + q] : 0.0;
+        rv[c] = in ? sg[(q / J) * GW + (q % J)] : 0.0;
+        hv[c] = h;
+        iv[c] = reg == VEST_REG_LF ? 1.0 / (h + lambda) : (h > 0.0 ? 1.0 / (2.0 * h) : 0.0);
+        corr[c] = 0.0;
+        dv[c] = 0.0;
+        mbits[c] = __ballot(in && cmask[base + q] != 0);
+        if (in) hdiag[base + q] = h;
+    }
+    for (int q = 0; q < B; ++q) {
+        const int oc = q / kWave, ol = q % kWave;
+        uint64_t mb = mbits[0];
+        double g = gv[0], r = rv[0], h = hv[0], iq = iv[0], cc = corr[0];
+#pragma unroll
+        for (int c = 1; c < CPL; ++c)
+            if (oc == c) {
+                mb = mbits[c];
+                g = gv[c];
+                r = rv[c];
+                h = hv[c];
+                iq = iv[c];
+                cc = corr[c];
+            }
+        if ((mb >> ol) & 1ull) continue;
+        g = readlane_d(g, ol);
+        r = readlane_d(r, ol);
+        h = readlane_d(h, ol);
+        iq = readlane_d(iq, ol);
+        cc = readlane_d(cc, ol);
+        // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
+        const double num = r - cc + g * h;
+        double nw;
+        if (reg == VEST_REG_LF) {
+            nw = num * iq;
+        } else {
+            const double gg = -2.0 * num;
+            nw = gg > lambda ? (lambda - gg) * iq : (gg < -lambda ? -(lambda + gg) * iq : 0.0);
+        }
+        const double dq = nw - g;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int q2 = lane + c * kWave;
+            if (c == oc && lane == ol) {
+                gv[c] = nw;
+                dv[c] = dq;
+            }
+            const double hq = q2 < B ? H(q2, q) : 0.0;
+            corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hq, dq, corr[c]) : corr[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q = lane + c * kWave;
+        if (q < B) {
+            core[base + q] = gv[c];
+            dprev[q] = dv[c];
+        }
+    }
+}
 
-    if constexpr (KEYS) {
-        // Delta(G_q) = sum (2 e + G_q w_q) G_q w_q = 2 G_q rr_q + G_q^2 H_qq  (Eq. 5)
-        for (int q = lane; q < B; q += kWave) {
-            const double g = core[base + q];
-            keys[base + q] = cmask[base + q] ? HUGE_VAL : 2.0 * g * RR(q) + g * g * H(q, q);
+// Core keys of a batch of slabs: Delta(G_q) = 2 G_q sum e w_q + G_q^2 sum w_q^2 (Eq. 5).
+// sum w_q^2 comes from the batch product (WITH_D) or from the Gram diagonals
+// kept by the last core sweep.
+template <int J, bool WITH_D>
+__global__ void __launch_bounds__(256) k_corekeys(const double *__restrict__ P, int w2, const double *__restrict__ core,
+                                                  const uint8_t *__restrict__ cmask, const double *__restrict__ hdiag,
+                                                  int64_t base, int nsb, double *__restrict__ keys)
+{
+    constexpr int PER = WITH_D ? 2 * J : J;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nsb * J * J) return;
+    const int b = q / (J * J), t = (q / J) % J, u = q % J;
+    const double r = P[(b * PER + t) * w2 + u];
+    const double d = WITH_D ? P[(b * PER + J + t) * w2 + J + u] : hdiag[base + q];
+    const double g = core[base + q];
+    keys[base + q] = cmask[base + q] ? HUGE_VAL : 2.0 * g * r + g * g * d;
+}
+
+template <int N, int J, typename T, bool WITH_D>
+static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out)
+{
+    constexpr int SB = key_slabs(N, J, WITH_D);
+    constexpr int PER = WITH_D ? 2 * J : J;
+    constexpr int W1 = round8(PER * SB), W2 = round8(2 * J);   // kp2 rows are [a | a^2] in both forms
+    const ModeLayout &L = c->lay[N - 1];
+    hipStream_t st = c->stream;
+    const int64_t Ilast = c->d.dims[N - 1];
+    const int blocks = (L.nwaves + 3) / 4;
+    const int64_t gchunks = (Ilast + kGramRows - 1) / kGramRows;
+    const int nslab = ipow(J, N - 2);
+    hipLaunchKernelGGL(k_kp2<J>, dim3((unsigned)((Ilast + 255) / 256)), dim3(256), 0, st, c->A[N - 1], Ilast, W2, c->kp);
+    for (int s0 = 0; s0 < nslab; s0 += SB) {
+        const int nsb = nslab - s0 < SB ? nslab - s0 : SB;
+        for (int b = 0; b < nsb; ++b) {
+            int s = s0 + b;
+            for (int m = N - 3; m >= 0; --m) {
+                a.blead[b * SlabArgs<N, J, T>::NL + m] = s % J;
+                s /= J;
+            }
         }
-    } else {
-        double corr[CPL];
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) corr[c] = 0.0;
-        for (int q = 0; q < B; ++q) {
-            const int64_t flat = base + q;
-            if (cmask[flat]) {
-                if (lane == 0) dprev[q] = 0.0;
-                continue;
-            }
-            const int oc = q / kWave;
-            double mine = corr[0];
-#pragma unroll
-            for (int c = 1; c < CPL; ++c)
-                if (oc == c) mine = corr[c];
-            const double cq = __shfl(mine, q % kWave, kWave);
-            const double hqq = H(q, q);
-            const double g = core[flat];
-            const double num = RR(q) - cq + g * hqq;
-            const double nw = coord_min(reg, lambda, num, hqq);
-            const double dq = nw - g;
-            if (lane == 0) {
-                core[flat] = nw;
-                dprev[q] = dq;
-            }
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int q2 = lane + c * kWave;
-                if (q2 > q && q2 < B) corr[c] = __builtin_fma(H(q2, q), dq, corr[c]);
-            }
-        }
+        if (blocks > 0)
+            hipLaunchKernelGGL((k_slabkeys<N, J, T, SB, WITH_D>), dim3(blocks), dim3(256), 0, st, a, nsb);
+        if (L.nlong > 0)
+            hipLaunchKernelGGL(k_slab_long<PER * SB>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
+                               c->rowbuf, c->ldrb);
+        hipLaunchKernelGGL((k_gram<W1, W2>), dim3((unsigned)gchunks), dim3(256), 0, st, c->rowbuf, c->ldrb, c->kp, W2,
+                           Ilast, c->gram_part);
+        hipLaunchKernelGGL(k_gramsum, dim3((W1 * W2 + 63) / 64), dim3(1024), 0, st, c->gram_part, gchunks, W1 * W2,
+                           c->gram);
+        const int64_t base = (int64_t)s0 * J * J;
+        hipLaunchKernelGGL((k_corekeys<J, WITH_D>), dim3((nsb * J * J + 255) / 256), dim3(256), 0, st, c->gram, W2,
+                           c->core, c->cmask, c->hdiag, base, nsb, key_out);
     }
 }
 
@@ -329,15 +587,13 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
         a.colA[m] = reinterpret_cast<const T *>(c->colA[m]);
         a.dimA[m] = I;
     }
-    a.Amid = f32 ? reinterpret_cast<const T *>(c->A32[N - 2]) : reinterpret_cast<const T *>(c->A[N - 2]);
+    a.ms = reinterpret_cast<const T *>(c->ms);
     a.Alast = f32 ? reinterpret_cast<const T *>(c->A32[last]) : reinterpret_cast<const T *>(c->A[last]);
     a.e = reinterpret_cast<T *>(c->e);
     a.dprev = c->dprev;
     a.rowbuf = c->rowbuf;
-    a.gw = GW;
+    a.ldrb = c->ldrb;
     a.partials = c->partials;
-    hipLaunchKernelGGL(k_kp<J>, dim3((unsigned)((Ilast + 255) / 256)), dim3(256), 0, st, c->A[last], Ilast, GW,
-                       c->kp);
 
     const int blocks = (L.nwaves + 3) / 4;
     const int64_t gchunks = (Ilast + kGramRows - 1) / kGramRows;
@@ -348,32 +604,35 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
             s /= J;
         }
     };
+    if (keys) {
+        if (c->hdiag_valid)
+            core_keys_batches<N, J, T, false>(c, a, key_out);
+        else
+            core_keys_batches<N, J, T, true>(c, a, key_out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_kp<J>, dim3((unsigned)((Ilast + 255) / 256)), dim3(256), 0, st, c->A[last], Ilast, GW,
+                       c->kp);
     for (int s = 0; s < nslab; ++s) {
         digits(s, a.lead);
-        a.has_prev = (!keys && s > 0) ? 1 : 0;
+        a.has_prev = s > 0 ? 1 : 0;
         if (s > 0) digits(s - 1, a.lprev);
         if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, true>), dim3(blocks), dim3(256), 0, st, a);
         if (L.nlong > 0)
-            hipLaunchKernelGGL(k_slab_long<J>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows, c->rowbuf,
-                               GW);
-        hipLaunchKernelGGL(k_gram<GW>, dim3((unsigned)gchunks), dim3(256), 0, st, c->rowbuf, c->kp, Ilast,
-                           c->gram_part);
-        hipLaunchKernelGGL(k_gramsum, dim3((GW * GW + 255) / 256), dim3(256), 0, st, c->gram_part, gchunks,
-                           GW * GW, c->gram);
+            hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
+                               c->rowbuf, c->ldrb);
+        hipLaunchKernelGGL((k_gram<GW, GW>), dim3((unsigned)gchunks), dim3(256), 0, st, c->rowbuf, c->ldrb, c->kp, GW,
+                           Ilast, c->gram_part);
+        hipLaunchKernelGGL(k_gramsum, dim3((GW * GW + 63) / 64), dim3(1024), 0, st, c->gram_part, gchunks, GW * GW,
+                           c->gram);
         const int64_t base = (int64_t)s * J * J;
-        if (keys)
-            hipLaunchKernelGGL((k_slabsolve<J, true>), dim3(1), dim3(64), 0, st, c->gram, c->core, c->cmask, base,
-                               c->d.lambda, c->d.reg, c->dprev, key_out);
-        else
-            hipLaunchKernelGGL((k_slabsolve<J, false>), dim3(1), dim3(64), 0, st, c->gram, c->core, c->cmask, base,
-                               c->d.lambda, c->d.reg, c->dprev, key_out);
+        hipLaunchKernelGGL(k_slabsolve<J>, dim3(1), dim3(64), 0, st, c->gram, c->core, c->cmask, base, c->d.lambda,
+                           c->d.reg, c->dprev, c->hdiag);
     }
-    if (!keys) {
-        // apply the last slab's change to the residual
-        a.has_prev = 1;
-        digits(nslab - 1, a.lprev);
-        if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, false>), dim3(blocks), dim3(256), 0, st, a);
-    }
+    // apply the last slab's change to the residual
+    a.has_prev = 1;
+    digits(nslab - 1, a.lprev);
+    if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, false>), dim3(blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -65,6 +65,17 @@ __device__ __forceinline__ void delta_vec(const T *__restrict__ Gp, const T (&r)
     for (int j = 0; j < J; ++j) d[j] = contract<N - 1, J, 0, T>(Gp + j * slice, r);
 }
 
+// Slot-ordered copy of a per-entry factor row, interleaved per wave: the J
+// values of the 64 slots of one (wave, k) step form one contiguous block of
+// 64 J elements, value t of every lane in a 64-element run (slot bases are
+// multiples of 64), so each of the J loads of a wave is one contiguous
+// 256/512-byte transaction inside a single block.
+template <int J>
+__host__ __device__ __forceinline__ int64_t ms_index(int64_t slot, int t)
+{
+    return (slot >> 6) * (int64_t)(64 * J) + t * 64 + (slot & 63);
+}
+
 // Load a factor row of J values with the widest aligned vector loads.
 template <int J, typename T>
 __device__ __forceinline__ void load_row(const T *__restrict__ p, T (&r)[J])

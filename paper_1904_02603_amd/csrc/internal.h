@@ -18,7 +18,7 @@
 //  * Per slot: the N-1 other-mode indices (int32, one array per mode, modes
 //    ascending), the value X_alpha (double or float), the canonical entry id.
 //  * The residual e = X - B lives in the slot order of mode N-1 (the "core
-//    layout"); other modes carry the slot of each entry in that layout.
+//    layout").
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,7 +71,6 @@ struct ModeLayout {
     int32_t *oidx[VEST_MAX_ORDER] = {};
     void *xval = nullptr;
     int32_t *perm = nullptr;
-    int32_t *eslot = nullptr;
     LongRow *longrows = nullptr;
 };
 
@@ -84,6 +83,31 @@ __host__ __device__ constexpr int round8(int x) { return (x + 7) / 8 * 8; }
 __host__ __device__ constexpr int gram_width(int J) { return round8(nacc_vc(J)); }
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Core-key passes handle key_slabs(N, J, d) slabs at once (J or 2 J
+// accumulators each, at most kKeyAcc per lane so that nothing spills, never
+// more than the J^(N-2) slabs there are).
+constexpr int kKeyAcc = 64;
+__host__ __device__ constexpr int key_slabs(int N, int J, bool with_d)
+{
+    return kKeyAcc / ((with_d ? 2 : 1) * J) < 1 ? 1
+           : (kKeyAcc / ((with_d ? 2 : 1) * J) > ipow(J, N - 2) ? ipow(J, N - 2) : kKeyAcc / ((with_d ? 2 : 1) * J));
+}
+__host__ __device__ constexpr int keys_width(int N, int J)
+{
+    return round8(2 * J * key_slabs(N, J, true)) > round8(J * key_slabs(N, J, false))
+               ? round8(2 * J * key_slabs(N, J, true))
+               : round8(J * key_slabs(N, J, false));
+}
+__host__ __device__ constexpr int keys_nacc(int N, int J)
+{
+    return 2 * J * key_slabs(N, J, true) > J * key_slabs(N, J, false) ? 2 * J * key_slabs(N, J, true)
+                                                                      : J * key_slabs(N, J, false);
+}
+__host__ __device__ constexpr int rowbuf_width(int N, int J)
+{
+    return gram_width(J) > keys_width(N, J) ? gram_width(J) : keys_width(N, J);
+}
 
 }  // namespace vest
 
@@ -105,10 +129,13 @@ struct vest_ctx {
     // workspace-resident derived state
     vest::ModeLayout lay[VEST_MAX_ORDER];
     void *e = nullptr;                // residual, core-layout slot order (T)
+    void *ms = nullptr;               // mode N-2 factor row of every core-layout slot (T)
+    double *hdiag = nullptr;          // diagonal of every slab's Gram matrix [|G|]
     void *Gp[VEST_MAX_ORDER] = {};    // core permuted for each mode (T)
     float *A32[VEST_MAX_ORDER] = {};  // FP32 copies of the factors (FP32 form)
     void *colA[VEST_MAX_ORDER] = {};  // column-major factor copies, modes < N-2 (T)
-    double *rowbuf = nullptr;         // [I_{N-1}][gram_width]
+    double *rowbuf = nullptr;         // [I_{N-1}][ldrb]
+    int ldrb = 0;
     double *kp = nullptr;             // [I_{N-1}][gram_width]
     double *gram_part = nullptr;      // [nchunks][gw*gw]
     double *gram = nullptr;           // [gw*gw]
@@ -130,6 +157,8 @@ struct vest_ctx {
     uint64_t gp_version[VEST_MAX_ORDER] = {};
     bool a32_valid[VEST_MAX_ORDER] = {};
     bool e_valid = false;
+    bool ms_valid = false;            // ms matches the current factors
+    bool hdiag_valid = false;         // hdiag matches the current factors
     bool keys_pending = false;
     double *key_core = nullptr;
     double *key_fac[VEST_MAX_ORDER] = {};

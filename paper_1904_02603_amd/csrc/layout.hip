@@ -120,20 +120,6 @@ __global__ void __launch_bounds__(256) k_scatter(const uint32_t *__restrict__ ro
     perm[slot] = (int32_t)e;
 }
 
-__global__ void __launch_bounds__(256) k_invperm(const int32_t *__restrict__ perm, int64_t nslots,
-                                                 int32_t *__restrict__ pos)
-{
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < nslots && perm[s] >= 0) pos[perm[s]] = (int32_t)s;
-}
-
-__global__ void __launch_bounds__(256) k_eslot(const int32_t *__restrict__ perm, int64_t nslots,
-                                               const int32_t *__restrict__ pos, int32_t *__restrict__ eslot)
-{
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < nslots) eslot[s] = perm[s] >= 0 ? pos[perm[s]] : -1;
-}
-
 static int bits_for(int64_t v)
 {
     int b = 1;
@@ -247,8 +233,7 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
     auto *counts = (uint32_t *)b.take(Imax * 4);
     auto *place = (RowPlace *)b.take(Imax * sizeof(RowPlace));
     auto *rptr = (int64_t *)b.take((Imax + 1) * 8);
-    auto *pos = (int32_t *)b.take(nnz * 4);
-    if (!ka || !kb || !va || !vb || !counts || !place || !rptr || !pos) return hipErrorOutOfMemory;
+    if (!ka || !kb || !va || !vb || !counts || !place || !rptr) return hipErrorOutOfMemory;
 
     // 1. bounds and finiteness
     DimsArg dm{};
@@ -332,13 +317,6 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
         CHECK_HIP(hipStreamSynchronize(st));
     }
 
-    // 4. slot of every entry in the core layout (mode N-1)
-    const ModeLayout &C = c->lay[N - 1];
-    hipLaunchKernelGGL(k_invperm, dim3(grid_for(C.nslots)), dim3(256), 0, st, C.perm, C.nslots, pos);
-    for (int n = 0; n < N - 1; ++n) {
-        const ModeLayout &L = c->lay[n];
-        hipLaunchKernelGGL(k_eslot, dim3(grid_for(L.nslots)), dim3(256), 0, st, L.perm, L.nslots, pos, L.eslot);
-    }
     return hipGetLastError();
 }
 

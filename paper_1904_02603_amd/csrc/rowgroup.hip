@@ -1,14 +1,15 @@
 // Row-group kernels over the per-mode layout of Omega:
 //   OP_SWEEP  one pass of Alg. 4 for mode n (factor update, Eq. 9 / Eq. 13)
 //   OP_KEYS   factor responsibility keys of mode n (Eq. 6)
-//   OP_RESID  residual e = X - B over the core layout (Eq. 7, Alg. 3 l. 1-3)
+//   OP_RESID  residual e = X - B over the core layout (Eq. 7, Alg. 3)
 //
 // One lane owns a slice of one row of mode n.  For every observed entry of
 // the slice it gathers the N-1 other-mode factor rows, forms delta_alpha
 // (Eq. 11) with the core operands streamed as wave-uniform scalar loads, and
 // accumulates the row statistics in registers:
 //   OP_SWEEP: c_j = sum X delta(j), V_jt = sum delta(j) delta(t)  (Eq. 9, 10)
-//   OP_KEYS : s_j = sum e delta(j), q_j = sum delta(j)^2
+//   OP_KEYS : s_j = sum e delta(j), q_j = sum delta(j)^2, with the residual
+//             e = X - a^(n)_{i_n} . delta recomputed from the same delta
 // The lanes of a row group are then summed by an xor butterfly and one lane
 // runs the FP64 row epilogue.  Because delta does not depend on A^(n), the
 // statistics are formed once per row and the Gauss-Seidel pass over j
@@ -37,8 +38,8 @@ struct RowArgs {
     float *A32;               // FP32 copy refreshed by OP_SWEEP (may be null)
     const uint32_t *mask;     // mode-n marking table
     double *partials;         // long-row chunk partials
-    T *e;                     // OP_RESID: out; OP_KEYS: in
-    const int32_t *eslot;     // OP_KEYS: slot of the entry in the core layout (null: same layout)
+    T *e;                     // OP_RESID: out
+    T *ms;                    // OP_RESID: out, mode N-2 factor row of every slot (see ms_index)
     double *keys;             // OP_KEYS: out [I_n * J]
 };
 
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
     const int row = has_row ? a.row_order[wi.first + grp] : 0;
 
     T own[J];
-    if constexpr (OP == OP_RESID) {
+    if constexpr (OP == OP_RESID || OP == OP_KEYS) {
         if (has_row) load_row<J, T>(a.own + (int64_t)row * J, own);
         else
 #pragma unroll
@@ -106,7 +107,11 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
         const int64_t sl = wi.base + (int64_t)k * kWave + lane;
         const int32_t i0 = a.oidx[0][sl];
         if (i0 < 0) {
-            if constexpr (OP == OP_RESID) a.e[sl] = T(0);
+            if constexpr (OP == OP_RESID) {
+                a.e[sl] = T(0);
+#pragma unroll
+                for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
+            }
             continue;
         }
         T r[N - 1][J];
@@ -124,7 +129,10 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
                 for (int u = t; u < J; ++u) s[J + sym<J>(t, u)] = vfma(d[t], d[u], s[J + sym<J>(t, u)]);
             }
         } else if constexpr (OP == OP_KEYS) {
-            const T ev = a.e[a.eslot ? (int64_t)a.eslot[sl] : sl];
+            T b = own[0] * d[0];
+#pragma unroll
+            for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
+            const T ev = a.xval[sl] - b;
 #pragma unroll
             for (int t = 0; t < J; ++t) {
                 s[t] = vfma(ev, d[t], s[t]);
@@ -135,6 +143,8 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
             for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
             a.e[sl] = a.xval[sl] - b;
+#pragma unroll
+            for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
         }
     }
     if constexpr (OP == OP_RESID) {
@@ -191,7 +201,7 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     a.mask = c->fmask[mode];
     a.partials = c->partials;
     a.e = reinterpret_cast<T *>(c->e);
-    a.eslot = L.eslot;
+    a.ms = reinterpret_cast<T *>(c->ms);
     a.keys = c->key_fac[mode];
     const T *Gp = reinterpret_cast<const T *>(c->Gp[mode]);
     const int blocks = (L.nwaves + 3) / 4;

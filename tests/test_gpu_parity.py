@@ -270,3 +270,20 @@ def test_fp32_form_rmse_within_1e4_of_oracle():
     gap = abs(gl["re"] - ol["re"]) / ol["re"]
     say("fp32 relative RMSE gap", gap, "factor rel err", rel_err(g.factors[0], o.factors[0]))
     assert gap <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[2], SHAPES[4]], ids=["N3J5", "N3J10", "N4J8"])
+def test_keys_without_a_preceding_core_sweep(shape):
+    # keys straight after init and after a factor sweep: the core keys cannot
+    # reuse the Gram diagonals of a core sweep and take the full statistics path
+    dims, ranks, nnz, zipf = shape
+    p = make(dims, ranks, nnz, 19, zipf)
+    g, o = pair(p, REG_LF, 0.05)
+    for step in range(2):
+        gck, gfk = g.responsibility()
+        ock, ofk = o.responsibility()
+        keys_close(gck, ock, "core keys, step %d" % step)
+        for n in range(len(dims)):
+            keys_close(gfk[n], ofk[n], "factor keys %d, step %d" % (n, step))
+        g.sweep_factor(0)
+        o.sweep_factor(0)
