@@ -114,6 +114,25 @@ def run_leg(p, precision, steps, warmup, target):
     }
 
 
+def measured_traffic():
+    """Calibrated HBM bytes per launch of the factor-sweep kernel from the
+    committed counter summary, or None if the kernel changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_k_rowgroup_sweep_planted-1e5^3-nnz1e7-r10_fp64.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = hashlib.sha256()
+    for f in ["rowgroup.hip", "device.h", "internal.h"]:
+        h.update(open(os.path.join(ROOT, "paper_1904_02603_amd", "csrc", f), "rb").read())
+    m = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", txt)
+    s = re.search(r"source-sha256: ([0-9a-f]+)", txt)
+    if not m or not s or s.group(1) != h.hexdigest()[:16]:
+        return None
+    return float(m.group(1))
+
+
 def cpu_baseline(p, seconds):
     """The FP64 oracle's Alg. 4 row update, timed on a bounded row sample."""
     import numpy as np
@@ -211,7 +230,8 @@ def main():
                    "prune": "manual ramp min(0.01 t, 0.1) toward %.2f" % args.target},
         "roofline": {"kernel": "k_rowgroup<OP_SWEEP> (factor sweep, one mode)", "bound": "alu",
                      "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f64"], "traffic": None,
+                     "frac": achieved / PEAK["f64"],
+                     "traffic": measured_traffic() if args.workload == DEFAULT_WORKLOAD and args.nnz is None else None,
                      "flops_per_launch": f64["sweep_flops_per_launch"],
                      "avg_launch_ms": f64["sweep_kernel_ms"]},
         "cpu_baseline": cpu,

@@ -82,7 +82,7 @@ int vest_workspace_bytes(const vest_desc *desc, size_t *bytes /* host out */);
  *   idx          nnz*N int32, entry-major (read during the call only)
  *   val          nnz FP64 observed values X_alpha (read during the call only)
  *   factors      host array of N device pointers, A_n with I_n*J_n FP64;
- *                in: initial values (Alg. 2 line 1), out: the model state
+ *                in: initial values (initialisation of Alg. 2), out: the model state
  *   core         prod(J_n) FP64, in/out
  *   factor_mask  host array of N device pointers, I_n uint32 words each
  *                (requires J_n <= 32); may hold earlier marks (resume)

@@ -193,7 +193,7 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle: prune count exceeds unmarked elements")
 
-    # ---- Alg. 2 lines 9-11
+    # ---- final normalisation of Alg. 2
     def normalize(self):
         self.lib.or_normalize(C.byref(self.st))
 

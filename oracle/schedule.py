@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY (see ``oracle.py``).
 
 Readings taken here:
   * iterations are counted t = 1, 2, ... and the pruning rate of iteration t is
-    pr_t = min(INIT_PR * t, MAX_PR) (Alg. 2 line 7; defaults 0.01 / 0.1 from
-    Sec. 3.3);
+    pr_t = min(INIT_PR * t, MAX_PR) (pruning step of Alg. 2; defaults 0.01 / 0.1
+    from Sec. 3.3);
   * a tensor T of |T| elements loses ceil(pr_t |T|) new elements per prune
     step, chosen among its unmarked ones; in the manual form the cumulative
     number of marks of T never exceeds ceil(s |T|) and pruning stops once the

@@ -14,8 +14,7 @@
  *   G[beta]             core, row-major flat index (last mode fastest)
  *   fmask_n[i*J_n + j]  1 = pruned (marking table, Sec. 3.3), same for cmask
  *
- * Readings of the paper that this file takes (each also listed in the design
- * notes):
+ * Readings of the paper that this file takes:
  *   - Within a factor row the update is Gauss-Seidel over j ascending, in
  *     place (Alg. 4).  delta, v and the numerator sum do not depend on row
  *     i_n of A^(n), so they are formed once per row instead of once per j;
@@ -29,8 +28,8 @@
  *   - ||X||_F in Eq. 4 is taken over the observed entries Omega.
  *   - Pruning ranks by the key Delta(e) = SSE(e set to 0) - SSE, which is
  *     ||X||^2 (RE(e)^2 - RE^2) and orders exactly like Resp(e) of Eq. 3 when
- *     RE > 0; ties are broken by ascending flat index.  Alg. 3 line 5 misses
- *     the square; Eq. 5 is used.
+ *     RE > 0; ties are broken by ascending flat index.  The core step of
+ *     Alg. 3 omits the square; Eq. 5 is used.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -158,7 +157,7 @@ double or_recon(const or_state *st, int64_t e)
     return b;
 }
 
-/* Residuals X_alpha - B(alpha) for every observed entry (Alg. 3 lines 1-3). */
+/* Residuals X_alpha - B(alpha) for every observed entry (first step of Alg. 3). */
 void or_residual(const or_state *st, double *res)
 {
     for (int64_t e = 0; e < st->nnz; ++e) res[e] = st->val[e] - or_recon(st, e);
@@ -409,7 +408,7 @@ int or_prune(or_state *st, const double *core_key, double *const *factor_key,
     return 0;
 }
 
-/* ---------------- Alg. 2 lines 9-11: column normalisation ---------------- */
+/* ---------------- Alg. 2, final step: column normalisation -------------- */
 /* A^(n) = U^(n) B^(n), columns of U unit length, B diagonal of column norms;
  * G <- G x_n B^(n).  A zero column stays zero and scales its core slice by 0. */
 void or_normalize(or_state *st)

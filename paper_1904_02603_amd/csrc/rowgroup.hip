@@ -80,7 +80,7 @@ __device__ __forceinline__ void row_epilogue(const RowArgs<N, J, T> &a, int row,
     }
 }
 
-template <int N, int J, typename T, int OP>
+template <int N, int J, typename T, int OP, int U>
 __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *__restrict__ Gp)
 {
     constexpr int NA = row_nacc<J, OP>();
@@ -103,48 +103,111 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
-    for (int k = 0; k < wi.K; ++k) {
-        const int64_t sl = wi.base + (int64_t)k * kWave + lane;
-        const int32_t i0 = a.oidx[0][sl];
-        if (i0 < 0) {
-            if constexpr (OP == OP_RESID) {
-                a.e[sl] = T(0);
+    // U entries per lane at a time: their index and value loads, then their
+    // factor-row gathers, are issued together, and the contraction reuses
+    // every core operand U times.  Slots past the lane's last entry are
+    // clamped onto it (loaded, not used); padding slots are skipped.
+    const int K = wi.K;
+    if constexpr (U == 1) {
+        for (int k = 0; k < K; ++k) {
+            const int64_t sl = wi.base + (int64_t)k * kWave + lane;
+            const int32_t i0 = a.oidx[0][sl];
+            if (i0 < 0) {
+                if constexpr (OP == OP_RESID) {
+                    a.e[sl] = T(0);
 #pragma unroll
-                for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
+                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
+                }
+                continue;
             }
-            continue;
-        }
-        T r[N - 1][J];
-        load_row<J, T>(a.fac[0] + (int64_t)i0 * J, r[0]);
+            T r[N - 1][J];
+            load_row<J, T>(a.fac[0] + (int64_t)i0 * J, r[0]);
 #pragma unroll
-        for (int m = 1; m < N - 1; ++m) load_row<J, T>(a.fac[m] + (int64_t)a.oidx[m][sl] * J, r[m]);
-        T d[J];
-        delta_vec<N, J, T>(Gp, r, d);
-        if constexpr (OP == OP_SWEEP) {
+            for (int m = 1; m < N - 1; ++m) load_row<J, T>(a.fac[m] + (int64_t)a.oidx[m][sl] * J, r[m]);
+            T d[J];
+            delta_vec<N, J, T>(Gp, r, d);
             const T x = a.xval[sl];
+            if constexpr (OP == OP_SWEEP) {
 #pragma unroll
-            for (int t = 0; t < J; ++t) {
-                s[t] = vfma(x, d[t], s[t]);
+                for (int t = 0; t < J; ++t) {
+                    s[t] = vfma(x, d[t], s[t]);
 #pragma unroll
-                for (int u = t; u < J; ++u) s[J + sym<J>(t, u)] = vfma(d[t], d[u], s[J + sym<J>(t, u)]);
+                    for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[t], d[v], s[J + sym<J>(t, v)]);
+                }
+            } else {
+                T b = own[0] * d[0];
+#pragma unroll
+                for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
+                if constexpr (OP == OP_KEYS) {
+                    const T ev = x - b;
+#pragma unroll
+                    for (int t = 0; t < J; ++t) {
+                        s[t] = vfma(ev, d[t], s[t]);
+                        s[J + t] = vfma(d[t], d[t], s[J + t]);
+                    }
+                } else {
+                    a.e[sl] = x - b;
+#pragma unroll
+                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
+                }
             }
-        } else if constexpr (OP == OP_KEYS) {
-            T b = own[0] * d[0];
+        }
+    } else
+    for (int k0 = 0; k0 < K; k0 += U) {
+        int64_t sl[U];
+        int32_t ii[U][N - 1];
+        bool ok[U];
 #pragma unroll
-            for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
-            const T ev = a.xval[sl] - b;
+        for (int u = 0; u < U; ++u) {
+            sl[u] = wi.base + (int64_t)(k0 + u < K ? k0 + u : K - 1) * kWave + lane;
 #pragma unroll
-            for (int t = 0; t < J; ++t) {
-                s[t] = vfma(ev, d[t], s[t]);
-                s[J + t] = vfma(d[t], d[t], s[J + t]);
+            for (int m = 0; m < N - 1; ++m) ii[u][m] = a.oidx[m][sl[u]];
+        }
+        T r[U][N - 1][J];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = (k0 + u < K) && ii[u][0] >= 0;
+#pragma unroll
+            for (int m = 0; m < N - 1; ++m)
+                load_row<J, T>(a.fac[m] + (int64_t)(ii[u][m] > 0 ? ii[u][m] : 0) * J, r[u][m]);
+        }
+        T x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = a.xval[sl[u]];
+        T d[U][J];
+        delta_vec_u<U, N, J, T>(Gp, r, d);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (OP == OP_RESID) {
+                if (k0 + u < K) {
+                    T b = own[0] * d[u][0];
+#pragma unroll
+                    for (int t = 1; t < J; ++t) b = vfma(own[t], d[u][t], b);
+                    a.e[sl[u]] = ok[u] ? x[u] - b : T(0);
+#pragma unroll
+                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl[u], t)] = ok[u] ? r[u][N - 2][t] : T(0);
+                }
+                continue;
             }
-        } else {
-            T b = own[0] * d[0];
+            if (!ok[u]) continue;
+            if constexpr (OP == OP_SWEEP) {
 #pragma unroll
-            for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
-            a.e[sl] = a.xval[sl] - b;
+                for (int t = 0; t < J; ++t) {
+                    s[t] = vfma(x[u], d[u][t], s[t]);
 #pragma unroll
-            for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
+                    for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[u][t], d[u][v], s[J + sym<J>(t, v)]);
+                }
+            } else {
+                T b = own[0] * d[u][0];
+#pragma unroll
+                for (int t = 1; t < J; ++t) b = vfma(own[t], d[u][t], b);
+                const T ev = x[u] - b;
+#pragma unroll
+                for (int t = 0; t < J; ++t) {
+                    s[t] = vfma(ev, d[u][t], s[t]);
+                    s[J + t] = vfma(d[u][t], d[u][t], s[J + t]);
+                }
+            }
         }
     }
     if constexpr (OP == OP_RESID) {
@@ -206,12 +269,15 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     const T *Gp = reinterpret_cast<const T *>(c->Gp[mode]);
     const int blocks = (L.nwaves + 3) / 4;
     if (blocks > 0) {
+        // one entry per lane: with two, the compiler hoists the shared core
+        // operands out of the loop and spills them to vector-register lanes
+        constexpr int U = 1;
         if (op == OP_SWEEP)
-            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
         else if (op == OP_KEYS)
-            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
         else
-            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
     }
     if (L.nlong > 0 && op != OP_RESID) {
         if (op == OP_SWEEP)

@@ -4,7 +4,7 @@ The per-iteration work runs in libvest; this module only decides how many
 elements each tensor loses per prune step and when pruning stops:
 
   * pruning rate of iteration t (t = 1, 2, ...): pr_t = min(INIT_PR t, MAX_PR)
-    with INIT_PR = 0.01, MAX_PR = 0.1 (Alg. 2 line 7, Sec. 3.3);
+    with INIT_PR = 0.01, MAX_PR = 0.1 (the pruning step of Alg. 2, Sec. 3.3);
   * a tensor of |T| elements loses ceil(pr_t |T|) unmarked elements per step;
     with a target sparsity s (VeST^man) the marks of a tensor never exceed
     ceil(s |T|) and pruning stops once the total sparsity reaches s;

@@ -14,7 +14,7 @@ which are not available here):
     evaluated at the observed entries, plus Gaussian noise of a stated variance
     or SNR; the rating-shaped workload clips 3 + 1.25 z / sqrt(|G|) to the
     integers 1..5;
-  * initial state: factors and core i.i.d. U[0, 1) (Alg. 2 line 1).
+  * initial state: factors and core i.i.d. U[0, 1) (initialisation of Alg. 2).
 """
 import math
 
@@ -97,7 +97,7 @@ def planted_model(ranks, dims, rng):
 
 
 def initial_state(dims, ranks, rng):
-    """Factors and core i.i.d. U[0, 1) (Alg. 2 line 1)."""
+    """Factors and core i.i.d. U[0, 1) (initialisation of Alg. 2)."""
     factors = [rng.random((dims[n], ranks[n])) for n in range(len(dims))]
     core = rng.random(tuple(ranks))
     return factors, core

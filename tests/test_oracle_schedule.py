@@ -1,4 +1,4 @@
-"""Pins of the oracle's pruning schedule (Alg. 2 line 7, Sec. 3.3)."""
+"""Pins of the oracle's pruning schedule (Alg. 2 pruning rate, Sec. 3.3)."""
 import numpy as np
 import pytest
 
