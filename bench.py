@@ -114,6 +114,30 @@ def run_leg(p, precision, steps, warmup, target):
     }
 
 
+def dense_accuracy(p, iters):
+    """RE and factor error of the FP32 / BF16 forms against the FP64 path after
+    `iters` full iterations without pruning (same start, same masks)."""
+    import torch
+    from paper_1904_02603_amd import vest
+    out, ref = {}, None
+    for name, prec in [("fp64", vest.FP64), ("fp32", vest.FP32), ("bf16", vest.BF16)]:
+        ctx = vest.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"],
+                               precision=prec)
+        for _ in range(iters):
+            ctx.iteration()
+        L = ctx.loss()
+        fac = [f.double().cpu() for f in ctx.factors]
+        ctx.close()
+        if ref is None:
+            ref = (L["re"], fac)
+            out["fp64_re"] = L["re"]
+            continue
+        err = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(fac, ref[1]))
+        out[name] = {"re": L["re"], "re_gap_vs_fp64": abs(L["re"] - ref[0]) / ref[0], "factor_rel_err": err}
+    out["iterations"] = iters
+    return out
+
+
 def measured_traffic():
     """Calibrated HBM bytes per launch of the factor-sweep kernel from the
     committed counter summary, or None if the kernel changed since."""
@@ -169,7 +193,10 @@ def main():
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--nnz", type=int, default=None, help="smaller nnz for a quick run (not a bench line)")
     ap.add_argument("--target", type=float, default=0.95)
-    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="FP64 leg only (no FP32 / BF16 legs)")
+    ap.add_argument("--accuracy-iters", type=int, default=5)
+    ap.add_argument("--legs", default="fp64,fp32,bf16",
+                    help="comma list of forms to time (the first must be fp64 for a bench line)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counters)")
@@ -197,14 +224,28 @@ def main():
     J = p["factors"][0].shape[1]
     log("  %.1f s: dims %s, nnz %d, ranks %d" % (time.perf_counter() - t0, [f.shape[0] for f in p["factors"]], nnz, J))
 
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    if args.no_fp32:
+        legs = ["fp64"]
+    if "fp64" not in legs:
+        # profiling runs of one low-precision form: time it, print nothing else
+        for name in legs:
+            r = run_leg(p, {"fp32": vest.FP32, "bf16": vest.BF16}[name], args.steps, args.warmup, args.target)
+            log("%s: %.3f ms/step, sweep kernel %.3f ms" % (name, r["ms_per_step"], r["sweep_kernel_ms"]))
+        return
     log("FP64 leg ...")
     f64 = run_leg(p, vest.FP64, args.steps, args.warmup, args.target)
     log("  %.3f ms/step, sweep kernel %.3f ms" % (f64["ms_per_step"], f64["sweep_kernel_ms"]))
-    f32 = None
-    if not args.no_fp32:
-        log("FP32 leg ...")
-        f32 = run_leg(p, vest.FP32, args.steps, args.warmup, args.target)
-        log("  %.3f ms/step, sweep kernel %.3f ms" % (f32["ms_per_step"], f32["sweep_kernel_ms"]))
+    lowp = {}
+    acc = None
+    if len(legs) > 1:
+        for name, prec in [(n, {"fp32": vest.FP32, "bf16": vest.BF16}[n]) for n in legs if n != "fp64"]:
+            log("%s leg ..." % name.upper())
+            lowp[name] = run_leg(p, prec, args.steps, args.warmup, args.target)
+            log("  %.3f ms/step, sweep kernel %.3f ms" % (lowp[name]["ms_per_step"], lowp[name]["sweep_kernel_ms"]))
+        if args.accuracy_iters > 0:
+            log("dense-phase accuracy (%d iterations, no pruning) ..." % args.accuracy_iters)
+            acc = dense_accuracy(p, args.accuracy_iters)
     cpu = None
     if args.cpu_seconds > 0:
         log("oracle CPU baseline ...")
@@ -239,12 +280,14 @@ def main():
         "sweep_only_value": f64["sweep_only_value"],
         "final_re": f64["final_re"],
     }
-    if f32 is not None:
-        a32 = f32["sweep_flops_per_launch"] / (f32["sweep_kernel_ms"] / 1e3) / 1e12
-        out["fp32"] = {"value": f32["value"], "ms_per_step": f32["ms_per_step"],
-                       "sweep_only_value": f32["sweep_only_value"], "breakdown_ms": f32["breakdown_ms"],
-                       "sweep_tflops": a32, "final_re": f32["final_re"],
-                       "re_gap_vs_fp64": abs(f32["final_re"] - f64["final_re"]) / f64["final_re"]}
+    for name, r in lowp.items():
+        out[name] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                     "sweep_only_value": r["sweep_only_value"], "breakdown_ms": r["breakdown_ms"],
+                     "sweep_tflops": r["sweep_flops_per_launch"] / (r["sweep_kernel_ms"] / 1e3) / 1e12,
+                     "final_re": r["final_re"],
+                     "re_gap_vs_fp64_pruned": abs(r["final_re"] - f64["final_re"]) / f64["final_re"]}
+    if acc is not None:
+        out["accuracy_dense"] = acc
     if args.nnz is not None:
         out["config"]["note"] = "reduced nnz: not the named workload"
     print(json.dumps(out))

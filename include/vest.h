@@ -53,13 +53,21 @@ enum { VEST_REG_LF = 0, VEST_REG_L1 = 1 };   /* Eq. 1 / Eq. 2 */
 
 /* Arithmetic of the delta contraction and of the row / residual sums.  The
  * per-coordinate division, the soft threshold and the responsibility keys
- * are FP64 in every form; factors and core stay FP64. */
-enum { VEST_FP64 = 0, VEST_FP32 = 1 };
+ * are FP64 in every form; factors and core stay FP64.
+ *   VEST_FP64  FP64 throughout
+ *   VEST_FP32  FP32 contraction and sums (order-3 factor sweeps run the first
+ *              contraction stage on FP32 matrix cores)
+ *   VEST_BF16  as VEST_FP32, except that in the order-3 factor sweep the
+ *              first contraction stage runs on BF16 matrix cores with FP32
+ *              accumulation: core and last other-mode factor row are each
+ *              split into two BF16 parts (hi + lo) and three products are
+ *              summed, about 16 significant operand bits */
+enum { VEST_FP64 = 0, VEST_FP32 = 1, VEST_BF16 = 2 };
 
 typedef struct {
     int32_t order;                     /* N, 2..VEST_MAX_ORDER                         */
     int32_t reg;                       /* VEST_REG_LF or VEST_REG_L1                   */
-    int32_t precision;                 /* VEST_FP64 or VEST_FP32                       */
+    int32_t precision;                 /* VEST_FP64, VEST_FP32 or VEST_BF16            */
     int32_t reserved;                  /* must be 0                                    */
     double lambda;                     /* lambda > 0, one value for core and factors
                                           (Eq. 1 / Eq. 2, Table 1)                     */

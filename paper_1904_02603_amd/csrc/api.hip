@@ -34,7 +34,7 @@ static int check_desc(const vest_desc *d)
     if (!d) { set_error("null descriptor"); return VEST_EINVAL; }
     if (d->order < 2 || d->order > VEST_MAX_ORDER) { set_error("order %d outside 2..%d", d->order, VEST_MAX_ORDER); return VEST_EINVAL; }
     if (d->reg != VEST_REG_LF && d->reg != VEST_REG_L1) { set_error("unknown regulariser %d", d->reg); return VEST_EINVAL; }
-    if (d->precision != VEST_FP64 && d->precision != VEST_FP32) { set_error("unknown precision %d", d->precision); return VEST_EINVAL; }
+    if (d->precision != VEST_FP64 && d->precision != VEST_FP32 && d->precision != VEST_BF16) { set_error("unknown precision %d", d->precision); return VEST_EINVAL; }
     if (d->reserved != 0) { set_error("reserved field must be 0"); return VEST_EINVAL; }
     if (!(d->lambda > 0.0) || !std::isfinite(d->lambda)) { set_error("lambda must be finite and > 0"); return VEST_EINVAL; }
     if (d->nnz < 1 || d->nnz >= (int64_t(1) << 31)) { set_error("nnz %lld outside 1..2^31-1", (long long)d->nnz); return VEST_EINVAL; }
@@ -124,7 +124,7 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     c->hdiag = (double *)take(c->G * 8);
     for (int n = 0; n < N; ++n) c->Gp[n] = take(c->G * ts);
     for (int n = 0; n < N; ++n)
-        c->A32[n] = c->d.precision == VEST_FP32 ? (float *)take(c->d.dims[n] * J * 4) : nullptr;
+        c->A32[n] = c->f32 ? (float *)take(c->d.dims[n] * J * 4) : nullptr;
     for (int m = 0; m + 2 < N; ++m) c->colA[m] = take(c->d.dims[m] * J * ts);
     const int gw = gram_width(J);
     const int64_t Il = c->d.dims[N - 1];
@@ -160,7 +160,8 @@ static void fill_ctx_shape(vest_ctx *c, const vest_desc *d)
     c->J = d->ranks[0];
     c->G = 1;
     for (int n = 0; n < c->N; ++n) c->G *= c->J;
-    c->tsize = d->precision == VEST_FP32 ? 4 : 8;
+    c->f32 = d->precision != VEST_FP64;
+    c->tsize = c->f32 ? 4 : 8;
 }
 
 #define CALL_HIP(c, x, where)                                       \
@@ -191,7 +192,7 @@ static int refresh_gp(vest_ctx *c)
 
 static int ensure_a32(vest_ctx *c)
 {
-    if (c->d.precision != VEST_FP32) return VEST_OK;
+    if (!c->f32) return VEST_OK;
     for (int n = 0; n < c->N; ++n)
         if (!c->a32_valid[n]) {
             CALL_HIP(c, launch_cast_factor(c, n), "cast factor");

@@ -640,7 +640,7 @@ static hipError_t core_pass(vest_ctx *c, bool keys, double *key_out)
 {
 #define VEST_CASE(NN, JJ)                                                                \
     if (c->N == NN && c->J == JJ)                                                        \
-        return c->d.precision == VEST_FP32 ? core_pass_t<NN, JJ, float>(c, keys, key_out) \
+        return c->f32 ? core_pass_t<NN, JJ, float>(c, keys, key_out) \
                                            : core_pass_t<NN, JJ, double>(c, keys, key_out);
     VEST_SHAPES(VEST_CASE)
 #undef VEST_CASE

@@ -9,6 +9,9 @@
 
 namespace vest {
 
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;   // matrix-core operand, 8 BF16
+typedef __attribute__((ext_vector_type(16))) float f32x16;   // 32 x 32 tile accumulator slice
+
 // Minimiser along one coordinate of  den x^2 - 2 num x + penalty(x)
 // (the element-wise rules of Sec. 3.4, always in FP64):
 //   L_F (Eq. 9 / Eq. 12): num / (den + lambda)

@@ -119,6 +119,7 @@ struct vest_ctx {
     int N = 0, J = 0;                 // uniform rank of the kernel instance
     int64_t G = 0;                    // |G|
     int tsize = 8;                    // bytes of the compute type
+    bool f32 = false;                 // compute type is float (FP32 and BF16 forms)
 
     // caller-owned model state
     double *A[VEST_MAX_ORDER] = {};

@@ -306,7 +306,7 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
         CHECK_HIP(hipMemsetAsync(L.perm, 0xff, ns * 4, st));
         OidxArg oa{};
         for (int m = 0; m < N - 1; ++m) oa.p[m] = L.oidx[m];
-        if (c->d.precision == VEST_FP32)
+        if (c->f32)
             hipLaunchKernelGGL(k_scatter<float>, dim3(grid_for(nnz)), dim3(256), 0, st, kb, vb, nnz, rptr, place,
                                L.waves, idx, N, n, val, oa, reinterpret_cast<float *>(L.xval), L.perm);
         else

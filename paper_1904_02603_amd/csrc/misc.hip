@@ -43,7 +43,7 @@ hipError_t launch_permute_core(vest_ctx *c, int mode)
 {
     Shape sh{c->N, c->J};
     const unsigned blocks = (unsigned)((c->G + 255) / 256);
-    if (c->d.precision == VEST_FP32)
+    if (c->f32)
         hipLaunchKernelGGL(k_permute<float>, dim3(blocks), dim3(256), 0, c->stream, c->core, sh, mode, c->G,
                            reinterpret_cast<float *>(c->Gp[mode]));
     else
@@ -129,7 +129,7 @@ hipError_t launch_loss(vest_ctx *c, double *dev_out)
     hipStream_t st = c->stream;
     double *part = c->red;
     const ModeLayout &L = c->lay[c->N - 1];
-    if (c->d.precision == VEST_FP32)
+    if (c->f32)
         hipLaunchKernelGGL((k_sum<float, 0>), dim3(kLossBlocks), dim3(256), 0, st,
                            reinterpret_cast<const float *>(c->e), L.nslots, part);
     else

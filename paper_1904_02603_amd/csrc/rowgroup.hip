@@ -239,6 +239,189 @@ __global__ void __launch_bounds__(64) k_rowgroup_long(RowArgs<N, J, T> a, const 
     }
 }
 
+// ------------------------------------------------------------ MFMA form
+// Order 3, factor sweep.  For the 64 slots of one step of a wave the first
+// stage of Eq. 11,
+//     T_alpha[(j, j')] = sum_{j''} G[j][j'][j''] a^(q)_{i_q j''}
+// (q = the last other mode, p the first), is the product of the core, read
+// as a (J^2 x J) matrix, with the (J x 64) matrix of the entries' A^(q) rows:
+// a 32 x 32 matrix-core tile has 32 pairs (j, j') as rows and one batch of
+// 32 entries as columns (batch 0: the entries of lanes 0..31, batch 1: those
+// of lanes 32..63).  A lane receives half of the rows of one column of each
+// batch; one permlane32 swap per register pair gives every lane all rows of
+// its own entry.  The second stage delta_j = sum_{j'} T[(j, j')] a^(p)_{i_p j'}
+// and the row statistics c, V run on the vector ALU in FP32, the epilogue in
+// FP64, as in the plain kernel.
+//   MF_BF16: BF16 operands, FP32 accumulation (K = 16 per op).  Core and
+//            A^(q) values are each split into x_hi = bf16(x) and
+//            x_lo = bf16(x - x_hi), and the tile is the sum of the three
+//            products lo.hi + hi.lo + hi.hi (the lo.lo term, of relative size
+//            2^-18, is dropped), so the operands carry about 16 significant
+//            bits instead of 8 (the split-BF16 scheme of Henry, Tang and
+//            Heinecke, "Leveraging the bfloat16 artificial intelligence
+//            datatype for higher-precision computations", ARITH 2019).
+//   MF_F32 : FP32 operands (K = 2 per op)
+enum { MF_BF16 = 0, MF_F32 = 1 };
+
+__device__ __forceinline__ void swap32(uint32_t &lo, uint32_t &hi)
+{
+    // lanes 32..63 of lo trade places with lanes 0..31 of hi
+    const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+    lo = r[0];
+    hi = r[1];
+}
+
+__device__ __forceinline__ void swap32(float &lo, float &hi)
+{
+    uint32_t a = __float_as_uint(lo), b = __float_as_uint(hi);
+    swap32(a, b);
+    lo = __uint_as_float(a);
+    hi = __uint_as_float(b);
+}
+
+template <int J, int MF>
+__global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, const float *__restrict__ Gp)
+{
+    static_assert(J <= 16, "one K block of 16 (BF16) or J/2 steps of 2 (FP32)");
+    constexpr int NA = nacc_vc(J);
+    constexpr int NT = (J * J + 31) / 32;
+    constexpr int KS = MF == MF_BF16 ? 1 : (J + 1) / 2;
+    constexpr int NS = MF == MF_BF16 ? 2 : 1;  // hi / lo parts
+    using AOp = typename std::conditional<MF == MF_BF16, bf16x8, float>::type;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (wave >= a.nwaves) return;  // whole waves only: the matrix ops need every lane
+    const WaveInfo wi = a.waves[wave];
+    const int grp = lane >> wi.glog;
+    const bool has_row = grp < wi.nrows;
+    const int row = has_row ? a.row_order[wi.first + grp] : 0;
+    const int h = lane >> 5;
+
+    // A operands: tile tau, row = pair P = 32 tau + (lane & 31); K index of
+    // element e is 8h + e (BF16) or 2 step + h (FP32); zero outside J^2 x J.
+    AOp ga[NS][NT][KS];
+#pragma unroll
+    for (int tau = 0; tau < NT; ++tau) {
+        const int P = 32 * tau + (lane & 31);
+        if constexpr (MF == MF_BF16) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * h + e;
+                float v = 0.0f;
+                if (P < J * J && k < J) v = Gp[P * J + k];
+                const __bf16 hi = (__bf16)v;
+                ga[0][tau][0][e] = hi;
+                ga[1][tau][0][e] = (__bf16)(v - (float)hi);
+            }
+        } else {
+#pragma unroll
+            for (int st = 0; st < KS; ++st) {
+                const int k = 2 * st + h;
+                float v = 0.0f;
+                if (P < J * J && k < J) v = Gp[P * J + k];
+                ga[0][tau][st] = v;
+            }
+        }
+    }
+
+    float s[NA];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) s[v] = 0.0f;
+
+    for (int k = 0; k < wi.K; ++k) {
+        const int64_t sl = wi.base + (int64_t)k * kWave + lane;
+        const int32_t i0 = a.oidx[0][sl];
+        const int32_t i1 = a.oidx[1][sl];  // 0 on padding slots
+        const bool ok = i0 >= 0;
+        float rp[J], rq[J];
+        load_row<J, float>(a.fac[0] + (int64_t)(ok ? i0 : 0) * J, rp);
+        load_row<J, float>(a.fac[1] + (int64_t)i1 * J, rq);
+#pragma unroll
+        for (int t = 0; t < J; ++t) rq[t] = ok ? rq[t] : 0.0f;  // zero column: T = 0, delta = 0
+        const float x = a.xval[sl];                               // 0 on padding slots
+
+        // B operands of the two batches from the lane's own row: lane l of
+        // batch b must hold K range h of the entry of lane 32 b + (l & 31).
+        AOp b0[NS][KS], b1[NS][KS];
+        if constexpr (MF == MF_BF16) {
+#pragma unroll
+            for (int part = 0; part < NS; ++part) {
+                bf16x8 k0, k1;  // K indices 0..7 and 8..15 of the own row
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float v0 = e < J ? rq[e] : 0.0f, v1 = 8 + e < J ? rq[8 + e] : 0.0f;
+                    const __bf16 h0 = (__bf16)v0, h1 = (__bf16)v1;
+                    k0[e] = part == 0 ? h0 : (__bf16)(v0 - (float)h0);
+                    k1[e] = part == 0 ? h1 : (__bf16)(v1 - (float)h1);
+                }
+                uint32_t u0[4], u1[4];
+                __builtin_memcpy(u0, &k0, 16);
+                __builtin_memcpy(u1, &k1, 16);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) swap32(u0[w], u1[w]);
+                __builtin_memcpy(&b0[part][0], u0, 16);
+                __builtin_memcpy(&b1[part][0], u1, 16);
+            }
+        } else {
+#pragma unroll
+            for (int st = 0; st < KS; ++st) {
+                b0[0][st] = rq[2 * st];
+                b1[0][st] = 2 * st + 1 < J ? rq[2 * st + 1] : 0.0f;
+                swap32(b0[0][st], b1[0][st]);
+            }
+        }
+
+        float d[J];
+#pragma unroll
+        for (int t = 0; t < J; ++t) d[t] = 0.0f;
+#pragma unroll
+        for (int tau = 0; tau < NT; ++tau) {
+            f32x16 D0 = {}, D1 = {};
+#pragma unroll
+            for (int st = 0; st < KS; ++st) {
+                if constexpr (MF == MF_BF16) {
+                    // small terms first
+                    D0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga[1][tau][st], b0[0][st], D0, 0, 0, 0);
+                    D1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga[1][tau][st], b1[0][st], D1, 0, 0, 0);
+                    D0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga[0][tau][st], b0[1][st], D0, 0, 0, 0);
+                    D1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga[0][tau][st], b1[1][st], D1, 0, 0, 0);
+                    D0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga[0][tau][st], b0[0][st], D0, 0, 0, 0);
+                    D1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga[0][tau][st], b1[0][st], D1, 0, 0, 0);
+                } else {
+                    D0 = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[0][tau][st], b0[0][st], D0, 0, 0, 0);
+                    D1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[0][tau][st], b1[0][st], D1, 0, 0, 0);
+                }
+            }
+            // register r of half hh holds row 8 (r / 4) + 4 hh + r % 4 of the
+            // tile; after the swap D0 holds the hh = 0 rows and D1 the hh = 1
+            // rows of the lane's own entry.
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                float lo = D0[r], hi = D1[r];
+                swap32(lo, hi);
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int P = 32 * tau + 8 * (r / 4) + 4 * hh + r % 4;
+                    if (P < J * J) d[P / J] = vfma(hh ? hi : lo, rp[P % J], d[P / J]);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < J; ++t) {
+            s[t] = vfma(x, d[t], s[t]);
+#pragma unroll
+            for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[t], d[v], s[J + sym<J>(t, v)]);
+        }
+    }
+    group_reduce<NA, float>(s, wi.glog);
+    if (wi.chunk >= 0) {
+        store_partial<NA, float>(a.partials, wi.chunk, s, lane);
+        return;
+    }
+    if (has_row && (lane & ((1 << wi.glog) - 1)) == 0) row_epilogue<3, J, float, OP_SWEEP, float>(a, row, s);
+}
+
 template <int N, int J, typename T>
 static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
 {
@@ -272,7 +455,18 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
         // one entry per lane: with two, the compiler hoists the shared core
         // operands out of the loop and spills them to vector-register lanes
         constexpr int U = 1;
-        if (op == OP_SWEEP)
+        bool done = false;
+        if constexpr (N == 3 && J <= 16 && std::is_same<T, float>::value) {
+            if (op == OP_SWEEP && c->d.precision == VEST_BF16) {
+                hipLaunchKernelGGL((k_rowgroup_mfma<J, MF_BF16>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+                done = true;
+            } else if (op == OP_SWEEP) {
+                hipLaunchKernelGGL((k_rowgroup_mfma<J, MF_F32>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+                done = true;
+            }
+        }
+        if (done) {
+        } else if (op == OP_SWEEP)
             hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
         else if (op == OP_KEYS)
             hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
@@ -294,7 +488,7 @@ hipError_t launch_rowgroup(vest_ctx *c, int mode, int op)
 {
 #define VEST_CASE(NN, JJ)                                                                 \
     if (c->N == NN && c->J == JJ)                                                         \
-        return c->d.precision == VEST_FP32 ? launch_rowgroup_t<NN, JJ, float>(c, mode, op) \
+        return c->f32 ? launch_rowgroup_t<NN, JJ, float>(c, mode, op) \
                                            : launch_rowgroup_t<NN, JJ, double>(c, mode, op);
     VEST_SHAPES(VEST_CASE)
 #undef VEST_CASE

@@ -16,7 +16,7 @@ MAX_ORDER = 10
 
 OK, EINVAL, ENOSPC, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 REG_LF, REG_L1 = 0, 1
-FP64, FP32 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
 
 EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
            "vest_responsibility", "vest_prune", "vest_loss", "vest_layout_stats",
