@@ -58,13 +58,15 @@ struct SlabArgs {
 // latencies -- streamed loads, then the column gathers of the leading factors
 // -- instead of a dependent chain per entry; padding slots are masked out of
 // the arithmetic by selects.
-constexpr int kSlabU = 2;
+// FP32 batches of four, FP64 of two (register budget).
+template <typename T>
+__host__ __device__ constexpr int slab_u() { return sizeof(T) == 4 ? 4 : 2; }
 
 template <int N, int J, typename T, bool ACC>
 __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 {
     constexpr int NA = nacc_vc(J);
-    constexpr int U = kSlabU;
+    constexpr int U = slab_u<T>();
     constexpr int NI = N > 2 ? N - 2 : 1;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -171,7 +173,7 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
 {
     constexpr int PER = WITH_D ? 2 * J : J;
     constexpr int NA = PER * SB;
-    constexpr int U = 2;
+    constexpr int U = slab_u<T>();
     constexpr int NL = SlabArgs<N, J, T>::NL;
     constexpr int NI = N > 2 ? N - 2 : 1;
     const int lane = threadIdx.x & (kWave - 1);
@@ -292,76 +294,55 @@ __global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, i
     out[q] = (T)A[i * J + j];
 }
 
-// Partial product of kGramRows rows: part[b] = sum_r rb_r^T kp_r (W1 x W2).
-// Thread (ti, tj) owns an 8 x 8 tile; rows are staged through LDS.
+// Partial product of kGramRows rows on the FP64 matrix cores:
+// part[b] = sum_r rb_r^T kp_r (W1 x W2).  Wave ti of the block owns the
+// 16-row band ti of the output and every 16 x 16 tile along it; one
+// v_mfma_f64_16x16x4 step consumes four rows r: lane l supplies
+// A[l % 16][l / 16] = rb[r0 + l / 16][16 ti + l % 16] and
+// B[l / 16][l % 16] = kp[r0 + l / 16][16 tj + l % 16], and tile element
+// (i, j) ends in lane 16 (i % 4) + j, register i / 4.  Columns past W1 / W2
+// and rows past nrows enter as zeros.
 template <int W1, int W2>
-__global__ void __launch_bounds__(256) k_gram(const double *__restrict__ rb, int ldrb, const double *__restrict__ kp,
-                                              int ldkp, int64_t nrows, double *__restrict__ part)
+__global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__restrict__ rb, int ldrb,
+                                                                 const double *__restrict__ kp, int ldkp,
+                                                                 int64_t nrows, double *__restrict__ part)
 {
-    constexpr int T1 = W1 / 8, T2 = W2 / 8;
-    constexpr int NT = T1 * T2;
-    static_assert(NT <= 256, "gram tile count");
-    constexpr int BR = 16;
-    __shared__ double sx[BR][W1];
-    __shared__ double sy[BR][W2];
+    constexpr int T2 = (W2 + 15) / 16;
+    static_assert(kGramRows % 4 == 0, "four rows per step");
+    const int lane = threadIdx.x & (kWave - 1), ti = threadIdx.x / kWave;
     const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
-    const int64_t r1 = r0 + kGramRows < nrows ? r0 + kGramRows : nrows;
-    const int t = threadIdx.x;
-    const int ti = t / T2, tj = t % T2;
-    double acc[8][8];
+    const int ci = 16 * ti + (lane & 15);
+    f64x4 acc[T2];
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
+    for (int tj = 0; tj < T2; ++tj) acc[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k = 0; k < kGramRows; k += 4) {
+        const int64_t r = r0 + k + (lane >> 4);
+        const bool inr = r < nrows;
+        const double av = (inr && ci < W1) ? rb[r * ldrb + ci] : 0.0;
+        double bv[T2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
-    for (int64_t b0 = r0; b0 < r1; b0 += BR) {
-        const int nb = (int)(r1 - b0 < BR ? r1 - b0 : BR);
-        constexpr int NX = (BR * W1 + 255) / 256, NY = (BR * W2 + 255) / 256;
-        double vx[NX], vy[NY];
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-            const int q = t + i * 256, rr = q / W1, cc = q % W1;
-            vx[i] = (q < BR * W1 && rr < nb) ? rb[(b0 + rr) * ldrb + cc] : 0.0;
+        for (int tj = 0; tj < T2; ++tj) {
+            const int cj = 16 * tj + (lane & 15);
+            bv[tj] = (inr && cj < W2) ? kp[r * ldkp + cj] : 0.0;
         }
 #pragma unroll
-        for (int i = 0; i < NY; ++i) {
-            const int q = t + i * 256, rr = q / W2, cc = q % W2;
-            vy[i] = (q < BR * W2 && rr < nb) ? kp[(b0 + rr) * ldkp + cc] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NX; ++i) {
-            const int q = t + i * 256;
-            if (q < BR * W1) sx[q / W1][q % W1] = vx[i];
-        }
-#pragma unroll
-        for (int i = 0; i < NY; ++i) {
-            const int q = t + i * 256;
-            if (q < BR * W2) sy[q / W2][q % W2] = vy[i];
-        }
-        __syncthreads();
-        if (t < NT) {
-            for (int rr = 0; rr < BR; ++rr) {
-                double x[8], y[8];
-#pragma unroll
-                for (int p = 0; p < 8; ++p) {
-                    x[p] = sx[rr][ti * 8 + p];
-                    y[p] = sy[rr][tj * 8 + p];
-                }
-#pragma unroll
-                for (int p = 0; p < 8; ++p)
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) acc[p][q] = __builtin_fma(x[p], y[q], acc[p][q]);
-            }
-        }
+        for (int tj = 0; tj < T2; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
     }
-    if (t < NT) {
-        double *o = part + (int64_t)blockIdx.x * W1 * W2;
+    double *o = part + (int64_t)blockIdx.x * W1 * W2;
 #pragma unroll
-        for (int p = 0; p < 8; ++p)
+    for (int tj = 0; tj < T2; ++tj) {
+        const int j = 16 * tj + (lane & 15);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) o[(ti * 8 + p) * W2 + tj * 8 + q] = acc[p][q];
+        for (int q = 0; q < 4; ++q) {
+            const int i = 16 * ti + 4 * q + (lane >> 4);
+            if (i < W1 && j < W2) o[i * W2 + j] = acc[tj][q];
+        }
     }
 }
+
+template <int W1>
+constexpr int gram_threads() { return 64 * ((W1 + 15) / 16); }
 
 // Fixed-order sum of the gram partials: block b owns outputs 64 b .. 64 b + 63;
 // wave w of the block sums partials w, w + 16, ... (coalesced across lanes),
@@ -555,7 +536,7 @@ static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out)
         if (L.nlong > 0)
             hipLaunchKernelGGL(k_slab_long<PER * SB>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
                                c->rowbuf, c->ldrb);
-        hipLaunchKernelGGL((k_gram<W1, W2>), dim3((unsigned)gchunks), dim3(256), 0, st, c->rowbuf, c->ldrb, c->kp, W2,
+        hipLaunchKernelGGL((k_gram<W1, W2>), dim3((unsigned)gchunks), dim3(gram_threads<W1>()), 0, st, c->rowbuf, c->ldrb, c->kp, W2,
                            Ilast, c->gram_part);
         hipLaunchKernelGGL(k_gramsum, dim3((W1 * W2 + 63) / 64), dim3(1024), 0, st, c->gram_part, gchunks, W1 * W2,
                            c->gram);
@@ -621,7 +602,7 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
         if (L.nlong > 0)
             hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
                                c->rowbuf, c->ldrb);
-        hipLaunchKernelGGL((k_gram<GW, GW>), dim3((unsigned)gchunks), dim3(256), 0, st, c->rowbuf, c->ldrb, c->kp, GW,
+        hipLaunchKernelGGL((k_gram<GW, GW>), dim3((unsigned)gchunks), dim3(gram_threads<GW>()), 0, st, c->rowbuf, c->ldrb, c->kp, GW,
                            Ilast, c->gram_part);
         hipLaunchKernelGGL(k_gramsum, dim3((GW * GW + 63) / 64), dim3(1024), 0, st, c->gram_part, gchunks, GW * GW,
                            c->gram);

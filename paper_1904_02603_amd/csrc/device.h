@@ -11,6 +11,7 @@ namespace vest {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;   // matrix-core operand, 8 BF16
 typedef __attribute__((ext_vector_type(16))) float f32x16;   // 32 x 32 tile accumulator slice
+typedef __attribute__((ext_vector_type(4))) double f64x4;    // 16 x 16 FP64 tile accumulator slice
 
 // Minimiser along one coordinate of  den x^2 - 2 num x + penalty(x)
 // (the element-wise rules of Sec. 3.4, always in FP64):
