@@ -138,6 +138,52 @@ def dense_accuracy(p, iters):
     return out
 
 
+def sparse_phase(p, frac, steps, precision):
+    """Factor sweeps of the pruned phase: fraction `frac` of every factor
+    matrix and of the core marked (zero) at random, sweeps timed with the
+    dense and with the gather contraction.  Algorithmic bytes of one sweep:
+    the streamed entries ((N-1) int32 indices + one value) plus every factor
+    matrix once (own read and written, the others read)."""
+    import numpy as np
+    import torch
+    from paper_1904_02603_amd import vest
+    rng = np.random.default_rng(20190402)
+    N, nnz = p["idx"].shape[1], p["idx"].shape[0]
+    fm = [rng.random(f.shape) < frac for f in p["factors"]]
+    cm = rng.random(p["core"].shape) < frac
+    fac = [f * (1 - m) for f, m in zip(p["factors"], fm)]
+    ctx = vest.VestContext(p["idx"], p["val"], fac, p["core"] * (1 - cm), reg=p["reg"], lam=p["lam"],
+                           precision=precision,
+                           fmask=[vest.bool_to_masks(torch.from_numpy(m)) for m in fm],
+                           cmask=torch.from_numpy(cm.astype(np.uint8)))
+    stream = torch.cuda.current_stream()
+    vb = 8 if precision == vest.FP64 else 4
+    alg = nnz * ((N - 1) * 4 + vb) + sum(f.shape[0] * f.shape[1] * 8 for f in p["factors"]) * (N + 1) / N
+    out = {"marked_fraction": frac, "algorithmic_bytes_per_sweep": alg}
+    for name, kern in [("dense", vest.KERNEL_DENSE), ("gather", vest.KERNEL_GATHER)]:
+        ctx.set_kernel(kern)
+        for n in range(N):
+            ctx.sweep_factor(n)
+        ev = []
+        for _ in range(steps):
+            for n in range(N):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx.sweep_factor(n)
+                b.record(stream)
+                ev.append((a, b))
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+        out[name + "_ms_per_sweep"] = ms
+        out[name + "_entry_updates_per_s"] = nnz / (ms / 1e3)
+    gbs = alg / (out["gather_ms_per_sweep"] / 1e3) / 1e9
+    out["gather_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s",
+                              "frac": gbs / HBM_PEAK}
+    ctx.close()
+    return out
+
+
 def measured_traffic():
     """Calibrated HBM bytes per launch of the factor-sweep kernel from the
     committed counter summary, or None if the kernel changed since."""
@@ -195,6 +241,8 @@ def main():
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--no-fp32", action="store_true", help="FP64 leg only (no FP32 / BF16 legs)")
     ap.add_argument("--accuracy-iters", type=int, default=5)
+    ap.add_argument("--sparse-frac", type=float, default=0.95,
+                    help="marked fraction of the pruned-phase sweep section (0 = skip it)")
     ap.add_argument("--legs", default="fp64,fp32,bf16",
                     help="comma list of forms to time (the first must be fp64 for a bench line)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -246,6 +294,14 @@ def main():
         if args.accuracy_iters > 0:
             log("dense-phase accuracy (%d iterations, no pruning) ..." % args.accuracy_iters)
             acc = dense_accuracy(p, args.accuracy_iters)
+    sparse = {}
+    if args.sparse_frac > 0:
+        for name in legs:
+            log("pruned-phase sweeps (%s, %.0f %% marked) ..." % (name, 100 * args.sparse_frac))
+            sparse[name] = sparse_phase(p, args.sparse_frac, args.steps,
+                                        {"fp64": vest.FP64, "fp32": vest.FP32, "bf16": vest.BF16}[name])
+            log("  dense %.3f ms, gather %.3f ms per sweep" % (sparse[name]["dense_ms_per_sweep"],
+                                                            sparse[name]["gather_ms_per_sweep"]))
     cpu = None
     if args.cpu_seconds > 0:
         log("oracle CPU baseline ...")
@@ -288,6 +344,8 @@ def main():
                      "re_gap_vs_fp64_pruned": abs(r["final_re"] - f64["final_re"]) / f64["final_re"]}
     if acc is not None:
         out["accuracy_dense"] = acc
+    if sparse:
+        out["pruned_phase"] = sparse
     if args.nnz is not None:
         out["config"]["note"] = "reduced nnz: not the named workload"
     print(json.dumps(out))

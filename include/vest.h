@@ -145,6 +145,20 @@ int vest_prune(vest_ctx *ctx, int64_t core_k, const int64_t *factor_k);
  * out is a host array of 5 doubles.  Synchronises the stream. */
 int vest_loss(vest_ctx *ctx, double *out);
 
+/* Contraction kernel of the factor sweeps, factor keys and residual passes
+ * (Eq. 11):
+ *   VEST_KERNEL_AUTO    per call, from the marked fractions of the factors
+ *                       (default)
+ *   VEST_KERNEL_DENSE   dense factored contraction over all of G
+ *   VEST_KERNEL_GATHER  pruned-phase form: only terms whose other-mode factor
+ *                       values are nonzero and whose core column
+ *                       G[.., j_n = any, ..] is nonzero; the core is staged in
+ *                       LDS
+ * Both forms compute the same sums up to rounding order.  VEST_EINVAL for an
+ * unknown value. */
+enum { VEST_KERNEL_AUTO = 0, VEST_KERNEL_DENSE = 1, VEST_KERNEL_GATHER = 2 };
+int vest_set_kernel(vest_ctx *ctx, int32_t kernel);
+
 /* Layout statistics of mode n (host out, 8 values): slots, padding slots,
  * waves, long rows, long-row chunks, max row length, rows, nnz. */
 int vest_layout_stats(vest_ctx *ctx, int32_t mode, int64_t *out);

@@ -74,11 +74,14 @@ int plan_workspace(const vest_desc *d, Plan *p)
     maxt = G > maxt ? G : maxt;
     p->max_tensor = maxt;
     for (int n = 0; n < N; ++n) {
+        // class-c waves (c >= 1) hold rows longer than kLaneTarget 2^(c-1):
+        // at most 2 nnz / (64 kLaneTarget) + 1 waves per class; long rows add
+        // at most 2 nnz / kChunk chunk waves
         p->slot_bound[n] = nnz + nnz / 8 + 1024 * kLaneTarget + 1024;
-        p->wave_bound[n] = d->dims[n] / 64 + nnz / 512 + 16;
+        p->wave_bound[n] = d->dims[n] / 64 + nnz / (32 * kLaneTarget) + 2 * nnz / kChunk + 16;
         p->long_bound[n] = nnz / kChunk + 1;
     }
-    p->chunk_bound = nnz / 1024 + 1;
+    p->chunk_bound = 2 * nnz / kChunk + 1;
     p->gram_chunks = (d->dims[N - 1] + kGramRows - 1) / kGramRows;
     size_t t1 = 0, t2 = 0;
     hipError_t e1 = hipcub::DeviceRadixSort::SortPairs(nullptr, t1, (uint32_t *)nullptr, (uint32_t *)nullptr,
@@ -432,6 +435,17 @@ int vest_loss(vest_ctx *c, double *out)
     out[2] = c->d.lambda * h[1];
     out[3] = out[0] + out[2];
     out[4] = c->xnorm2 > 0 ? std::sqrt(out[0] / c->xnorm2) : 0.0;
+    return VEST_OK;
+}
+
+int vest_set_kernel(vest_ctx *c, int32_t kernel)
+{
+    if (!c) { set_error("null context"); return VEST_EINVAL; }
+    if (kernel != VEST_KERNEL_AUTO && kernel != VEST_KERNEL_DENSE && kernel != VEST_KERNEL_GATHER) {
+        set_error("unknown kernel policy %d", kernel);
+        return VEST_EINVAL;
+    }
+    c->kernel_policy = kernel;
     return VEST_OK;
 }
 

@@ -69,51 +69,6 @@ __device__ __forceinline__ void delta_vec(const T *__restrict__ Gp, const T (&r)
     for (int j = 0; j < J; ++j) d[j] = contract<N - 1, J, 0, T>(Gp + j * slice, r);
 }
 
-// The same contraction for U entries at once: every core operand is loaded
-// once and used for U fused multiply-adds.
-template <int U, int NO, int J, int D, typename T>
-__device__ __forceinline__ void contract_u(const T *__restrict__ G, const T (&r)[U][NO][J], T (&out)[U])
-{
-    if constexpr (D == NO - 1) {
-        {
-            const T g = G[0];
-#pragma unroll
-            for (int u = 0; u < U; ++u) out[u] = g * r[u][D][0];
-        }
-#pragma unroll
-        for (int o = 1; o < J; ++o) {
-            const T g = G[o];
-#pragma unroll
-            for (int u = 0; u < U; ++u) out[u] = vfma(g, r[u][D][o], out[u]);
-        }
-    } else {
-        constexpr int stride = ipow(J, NO - 1 - D);
-        T in[U];
-        contract_u<U, NO, J, D + 1, T>(G, r, in);
-#pragma unroll
-        for (int u = 0; u < U; ++u) out[u] = in[u] * r[u][D][0];
-#pragma unroll
-        for (int o = 1; o < J; ++o) {
-            contract_u<U, NO, J, D + 1, T>(G + o * stride, r, in);
-#pragma unroll
-            for (int u = 0; u < U; ++u) out[u] = vfma(in[u], r[u][D][o], out[u]);
-        }
-    }
-}
-
-template <int U, int N, int J, typename T>
-__device__ __forceinline__ void delta_vec_u(const T *__restrict__ Gp, const T (&r)[U][N - 1][J], T (&d)[U][J])
-{
-    constexpr int slice = ipow(J, N - 1);
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        T o[U];
-        contract_u<U, N - 1, J, 0, T>(Gp + j * slice, r, o);
-#pragma unroll
-        for (int u = 0; u < U; ++u) d[u][j] = o[u];
-    }
-}
-
 // Slot-ordered copy of a per-entry factor row, interleaved per wave: the J
 // values of the 64 slots of one (wave, k) step form one contiguous block of
 // 64 J elements, value t of every lane in a 64-element run (slot bases are

@@ -36,7 +36,7 @@
 namespace vest {
 
 constexpr int kWave = 64;
-constexpr int kLaneTarget = 32;                   // entries per lane in a row group
+constexpr int kLaneTarget = 16;                   // entries per lane in a row group
 constexpr int kChunk = kWave * kLaneTarget;       // entries per long-row chunk
 constexpr int kGramRows = 128;                    // rows per gram partial
 constexpr int kLossBlocks = 1024;                 // fixed grid of the loss reductions
@@ -120,6 +120,7 @@ struct vest_ctx {
     int64_t G = 0;                    // |G|
     int tsize = 8;                    // bytes of the compute type
     bool f32 = false;                 // compute type is float (FP32 and BF16 forms)
+    int kernel_policy = 0;            // VEST_KERNEL_AUTO / _DENSE / _GATHER
 
     // caller-owned model state
     double *A[VEST_MAX_ORDER] = {};

@@ -33,6 +33,7 @@ struct RowArgs {
     const int32_t *oidx[N - 1];
     const T *xval;
     const T *fac[N - 1];      // other modes, ascending, compute type
+    const uint32_t *omask[N - 1];  // their marking tables (gather form)
     const T *own;             // mode-n factor in compute type (OP_RESID)
     double *A;                // mode-n FP64 factor
     float *A32;               // FP32 copy refreshed by OP_SWEEP (may be null)
@@ -80,10 +81,118 @@ __device__ __forceinline__ void row_epilogue(const RowArgs<N, J, T> &a, int row,
     }
 }
 
-template <int N, int J, typename T, int OP, int U>
+// Pruned-phase contraction (Eq. 11 restricted to nonzero terms).  The core
+// is staged in LDS with the mode-n index innermost, Gt[(o_0 .. o_{N-2}) J + j]
+// (o_m = index of the m-th other mode), plus one bit per core column
+// (o_0 .. o_{N-2}) that has a nonzero value.  Each lane walks only the
+// combinations of nonzero values of its entry's other-mode rows whose core
+// column is nonzero, so the work per entry is proportional to the number of
+// surviving terms instead of J^N.
+// r[b] for a per-lane b, as a sum with exactly one nonzero term (a select
+// chain would be folded back into a dynamically indexed array, which lives
+// in scratch memory).
+template <int J, typename T>
+__device__ __forceinline__ T pick(const T (&r)[J], int b)
+{
+    T v = r[0] * (b == 0 ? T(1) : T(0));
+#pragma unroll
+    for (int t = 1; t < J; ++t) v = vfma(r[t], b == t ? T(1) : T(0), v);
+    return v;
+}
+
+template <int L, int N, int J, typename T>
+__device__ __forceinline__ void gather_level(const T *__restrict__ Gt, const uint32_t *__restrict__ Gnz,
+                                             const T (&r)[N - 1][J], const uint32_t (&m)[N - 1], T w, int o,
+                                             T (&d)[J])
+{
+    uint32_t bits = m[L];
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1;
+        const T v = w * pick<J, T>(r[L], b);
+        const int oo = o * J + b;
+        if constexpr (L == N - 2) {
+            if ((Gnz[oo >> 5] >> (oo & 31)) & 1u) {
+                const T *g = Gt + oo * J;
+#pragma unroll
+                for (int j = 0; j < J; ++j) d[j] = vfma(v, g[j], d[j]);
+            }
+        } else {
+            gather_level<L + 1, N, J, T>(Gt, Gnz, r, m, v, oo, d);
+        }
+    }
+}
+
+// delta of one entry in the gather form.  The marking tables of the other
+// modes (one 32-bit word per row, small enough to stay in L2) are read
+// first; the factor rows are fetched only when every other-mode row still
+// has an unmarked element, otherwise delta = 0 without touching them.
+template <int N, int J, typename T>
+__device__ __forceinline__ void delta_gather(const T *__restrict__ Gt, const uint32_t *__restrict__ Gnz,
+                                             const T *const (&fac)[N - 1], const uint32_t *const (&omask)[N - 1],
+                                             const int32_t (&ii)[N - 1], T (&r)[N - 1][J], T (&d)[J])
+{
+    constexpr uint32_t full = J == 32 ? 0xffffffffu : (1u << J) - 1u;
+#pragma unroll
+    for (int j = 0; j < J; ++j) d[j] = T(0);
+    uint32_t m[N - 1];
+    bool live = true;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        m[k] = ~omask[k][ii[k]] & full;
+        live = live && m[k] != 0u;
+    }
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        load_row<J, T>(fac[k] + (int64_t)ii[k] * J, r[k]);
+        uint32_t b = 0;
+#pragma unroll
+        for (int t = 0; t < J; ++t) b |= (r[k][t] != T(0) ? 1u : 0u) << t;
+        m[k] &= b;
+    }
+    gather_level<0, N, J, T>(Gt, Gnz, r, m, T(1), 0, d);
+}
+
+template <int N, int J, typename T>
+__host__ __device__ constexpr size_t gather_lds_bytes()
+{
+    return (size_t)ipow(J, N) * sizeof(T) + ((size_t)ipow(J, N - 1) + 31) / 32 * 4;
+}
+
+// Block-cooperative staging of the mode-permuted core Gp ([j][o], row-major)
+// into Gt ([o][j]) and the nonzero-column bits.
+template <int N, int J, typename T>
+__device__ __forceinline__ void stage_core(const T *__restrict__ Gp, T *Gt, uint32_t *Gnz)
+{
+    constexpr int S = ipow(J, N - 1);
+    constexpr int NW = (S + 31) / 32;
+    for (int q = threadIdx.x; q < NW; q += blockDim.x) Gnz[q] = 0u;
+    for (int q = threadIdx.x; q < S * J; q += blockDim.x) {
+        const int j = q / S, o = q % S;
+        Gt[o * J + j] = Gp[q];
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < S; o += blockDim.x) {
+        bool nz = false;
+#pragma unroll
+        for (int j = 0; j < J; ++j) nz |= Gt[o * J + j] != T(0);
+        if (nz) atomicOr(&Gnz[o >> 5], 1u << (o & 31));
+    }
+    __syncthreads();
+}
+
+// GA = false: dense factored contraction, core operands as scalar loads.
+// GA = true : pruned-phase gather contraction from LDS (dynamic LDS of
+//             gather_lds_bytes<N, J, T>() bytes).
+template <int N, int J, typename T, int OP, bool GA>
 __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *__restrict__ Gp)
 {
     constexpr int NA = row_nacc<J, OP>();
+    extern __shared__ __align__(16) char smem[];
+    T *Gt = reinterpret_cast<T *>(smem);
+    uint32_t *Gnz = reinterpret_cast<uint32_t *>(smem + (size_t)ipow(J, N) * sizeof(T));
+    if constexpr (GA) stage_core<N, J, T>(Gp, Gt, Gnz);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (wave >= a.nwaves) return;
@@ -103,110 +212,60 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
-    // U entries per lane at a time: their index and value loads, then their
-    // factor-row gathers, are issued together, and the contraction reuses
-    // every core operand U times.  Slots past the lane's last entry are
-    // clamped onto it (loaded, not used); padding slots are skipped.
     const int K = wi.K;
-    if constexpr (U == 1) {
-        for (int k = 0; k < K; ++k) {
-            const int64_t sl = wi.base + (int64_t)k * kWave + lane;
-            const int32_t i0 = a.oidx[0][sl];
-            if (i0 < 0) {
-                if constexpr (OP == OP_RESID) {
-                    a.e[sl] = T(0);
+    for (int k = 0; k < K; ++k) {
+        const int64_t sl = wi.base + (int64_t)k * kWave + lane;
+        const int32_t i0 = a.oidx[0][sl];
+        if (i0 < 0) {
+            if constexpr (OP == OP_RESID) {
+                a.e[sl] = T(0);
 #pragma unroll
-                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
-                }
-                continue;
+                for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
             }
-            T r[N - 1][J];
+            continue;
+        }
+        T r[N - 1][J];
+        T d[J];
+        if constexpr (GA) {
+            int32_t ii[N - 1];
+            ii[0] = i0;
+#pragma unroll
+            for (int m = 1; m < N - 1; ++m) ii[m] = a.oidx[m][sl];
+            delta_gather<N, J, T>(Gt, Gnz, a.fac, a.omask, ii, r, d);
+            if constexpr (OP == OP_RESID) {
+                // the slot copy of the mode N-2 row must hold the values even
+                // when delta vanished without loading them
+                load_row<J, T>(a.fac[N - 2] + (int64_t)ii[N - 2] * J, r[N - 2]);
+            }
+        } else {
             load_row<J, T>(a.fac[0] + (int64_t)i0 * J, r[0]);
 #pragma unroll
             for (int m = 1; m < N - 1; ++m) load_row<J, T>(a.fac[m] + (int64_t)a.oidx[m][sl] * J, r[m]);
-            T d[J];
             delta_vec<N, J, T>(Gp, r, d);
-            const T x = a.xval[sl];
-            if constexpr (OP == OP_SWEEP) {
+        }
+        const T x = a.xval[sl];
+        if constexpr (OP == OP_SWEEP) {
+#pragma unroll
+            for (int t = 0; t < J; ++t) {
+                s[t] = vfma(x, d[t], s[t]);
+#pragma unroll
+                for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[t], d[v], s[J + sym<J>(t, v)]);
+            }
+        } else {
+            T b = own[0] * d[0];
+#pragma unroll
+            for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
+            if constexpr (OP == OP_KEYS) {
+                const T ev = x - b;
 #pragma unroll
                 for (int t = 0; t < J; ++t) {
-                    s[t] = vfma(x, d[t], s[t]);
-#pragma unroll
-                    for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[t], d[v], s[J + sym<J>(t, v)]);
+                    s[t] = vfma(ev, d[t], s[t]);
+                    s[J + t] = vfma(d[t], d[t], s[J + t]);
                 }
             } else {
-                T b = own[0] * d[0];
+                a.e[sl] = x - b;
 #pragma unroll
-                for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
-                if constexpr (OP == OP_KEYS) {
-                    const T ev = x - b;
-#pragma unroll
-                    for (int t = 0; t < J; ++t) {
-                        s[t] = vfma(ev, d[t], s[t]);
-                        s[J + t] = vfma(d[t], d[t], s[J + t]);
-                    }
-                } else {
-                    a.e[sl] = x - b;
-#pragma unroll
-                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
-                }
-            }
-        }
-    } else
-    for (int k0 = 0; k0 < K; k0 += U) {
-        int64_t sl[U];
-        int32_t ii[U][N - 1];
-        bool ok[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            sl[u] = wi.base + (int64_t)(k0 + u < K ? k0 + u : K - 1) * kWave + lane;
-#pragma unroll
-            for (int m = 0; m < N - 1; ++m) ii[u][m] = a.oidx[m][sl[u]];
-        }
-        T r[U][N - 1][J];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            ok[u] = (k0 + u < K) && ii[u][0] >= 0;
-#pragma unroll
-            for (int m = 0; m < N - 1; ++m)
-                load_row<J, T>(a.fac[m] + (int64_t)(ii[u][m] > 0 ? ii[u][m] : 0) * J, r[u][m]);
-        }
-        T x[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = a.xval[sl[u]];
-        T d[U][J];
-        delta_vec_u<U, N, J, T>(Gp, r, d);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if constexpr (OP == OP_RESID) {
-                if (k0 + u < K) {
-                    T b = own[0] * d[u][0];
-#pragma unroll
-                    for (int t = 1; t < J; ++t) b = vfma(own[t], d[u][t], b);
-                    a.e[sl[u]] = ok[u] ? x[u] - b : T(0);
-#pragma unroll
-                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl[u], t)] = ok[u] ? r[u][N - 2][t] : T(0);
-                }
-                continue;
-            }
-            if (!ok[u]) continue;
-            if constexpr (OP == OP_SWEEP) {
-#pragma unroll
-                for (int t = 0; t < J; ++t) {
-                    s[t] = vfma(x[u], d[u][t], s[t]);
-#pragma unroll
-                    for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[u][t], d[u][v], s[J + sym<J>(t, v)]);
-                }
-            } else {
-                T b = own[0] * d[u][0];
-#pragma unroll
-                for (int t = 1; t < J; ++t) b = vfma(own[t], d[u][t], b);
-                const T ev = x[u] - b;
-#pragma unroll
-                for (int t = 0; t < J; ++t) {
-                    s[t] = vfma(ev, d[u][t], s[t]);
-                    s[J + t] = vfma(d[u][t], d[u][t], s[J + t]);
-                }
+                for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
             }
         }
     }
@@ -422,6 +481,27 @@ __global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, c
     if (has_row && (lane & ((1 << wi.glog) - 1)) == 0) row_epilogue<3, J, float, OP_SWEEP, float>(a, row, s);
 }
 
+// Kernel choice for the contraction of mode `mode` (the factors of the other
+// modes enter).  AUTO compares the expected number of surviving terms per
+// entry, E = prod_{k != mode} J d_k (d_k = unmarked fraction of A^(k)), each
+// costing J LDS reads and fused multiply-adds, with the dense contraction's
+// sum_{m=2..N} J^m operations (a quarter of that on the matrix-core form).
+static bool use_gather(const vest_ctx *c, int mode, bool dense_on_mfma)
+{
+    if (c->kernel_policy == VEST_KERNEL_DENSE) return false;
+    if (c->kernel_policy == VEST_KERNEL_GATHER) return true;
+    const int N = c->N, J = c->J;
+    double E = 1.0, D = 0.0, p = J;
+    for (int k = 0; k < N; ++k) {
+        if (k == mode) continue;
+        const double size = (double)c->d.dims[k] * J;
+        E *= J * (1.0 - (double)c->marked_fac[k] / size);
+    }
+    for (int m = 2; m <= N; ++m) D += (p *= J);
+    if (dense_on_mfma) D *= 0.25;
+    return 3.0 * E * J < D;
+}
+
 template <int N, int J, typename T>
 static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
 {
@@ -438,6 +518,7 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
         if (k == mode) continue;
         a.oidx[m] = L.oidx[m];
         a.fac[m] = f32 ? reinterpret_cast<const T *>(c->A32[k]) : reinterpret_cast<const T *>(c->A[k]);
+        a.omask[m] = c->fmask[k];
         ++m;
     }
     a.xval = reinterpret_cast<const T *>(L.xval);
@@ -451,27 +532,35 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     a.keys = c->key_fac[mode];
     const T *Gp = reinterpret_cast<const T *>(c->Gp[mode]);
     const int blocks = (L.nwaves + 3) / 4;
+    const bool ga = use_gather(c, mode, (N == 3 && J <= 16 && std::is_same<T, float>::value && op == OP_SWEEP));
+    const size_t lds = ga ? gather_lds_bytes<N, J, T>() : 0;
     if (blocks > 0) {
-        // one entry per lane: with two, the compiler hoists the shared core
-        // operands out of the loop and spills them to vector-register lanes
-        constexpr int U = 1;
         bool done = false;
         if constexpr (N == 3 && J <= 16 && std::is_same<T, float>::value) {
-            if (op == OP_SWEEP && c->d.precision == VEST_BF16) {
-                hipLaunchKernelGGL((k_rowgroup_mfma<J, MF_BF16>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
-                done = true;
-            } else if (op == OP_SWEEP) {
-                hipLaunchKernelGGL((k_rowgroup_mfma<J, MF_F32>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+            if (!ga && op == OP_SWEEP) {
+                if (c->d.precision == VEST_BF16)
+                    hipLaunchKernelGGL((k_rowgroup_mfma<J, MF_BF16>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+                else
+                    hipLaunchKernelGGL((k_rowgroup_mfma<J, MF_F32>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
                 done = true;
             }
         }
         if (done) {
-        } else if (op == OP_SWEEP)
-            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
-        else if (op == OP_KEYS)
-            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
-        else
-            hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, U>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+        } else if (ga) {
+            if (op == OP_SWEEP)
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
+            else if (op == OP_KEYS)
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
+            else
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
+        } else {
+            if (op == OP_SWEEP)
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+            else if (op == OP_KEYS)
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+            else
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+        }
     }
     if (L.nlong > 0 && op != OP_RESID) {
         if (op == OP_SWEEP)

@@ -17,9 +17,10 @@ MAX_ORDER = 10
 OK, EINVAL, ENOSPC, EDEVICE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 REG_LF, REG_L1 = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
+KERNEL_AUTO, KERNEL_DENSE, KERNEL_GATHER = 0, 1, 2
 
 EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
-           "vest_responsibility", "vest_prune", "vest_loss", "vest_layout_stats",
+           "vest_responsibility", "vest_prune", "vest_loss", "vest_set_kernel", "vest_layout_stats",
            "vest_destroy", "vest_strerror", "vest_last_error"]
 
 
@@ -62,6 +63,7 @@ def load_library(path=LIB_PATH):
     lib.vest_responsibility.argtypes = [vp, vp, vp]
     lib.vest_prune.argtypes = [vp, i64, vp]
     lib.vest_loss.argtypes = [vp, vp]
+    lib.vest_set_kernel.argtypes = [vp, i32]
     lib.vest_layout_stats.argtypes = [vp, i32, vp]
     lib.vest_destroy.argtypes = [vp]
     lib.vest_strerror.argtypes = [C.c_int]
@@ -69,7 +71,8 @@ def load_library(path=LIB_PATH):
     lib.vest_last_error.argtypes = []
     lib.vest_last_error.restype = C.c_char_p
     for name in ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
-                 "vest_responsibility", "vest_prune", "vest_loss", "vest_layout_stats", "vest_destroy"]:
+                 "vest_responsibility", "vest_prune", "vest_loss", "vest_set_kernel", "vest_layout_stats",
+                 "vest_destroy"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -197,6 +200,10 @@ class VestContext:
         for n in range(self.N):
             self.sweep_factor(n)
         self.sweep_core()
+
+    def set_kernel(self, kernel):
+        """Contraction kernel policy: KERNEL_AUTO, KERNEL_DENSE or KERNEL_GATHER."""
+        _check(self.lib.vest_set_kernel(self.ctx, int(kernel)), "vest_set_kernel")
 
     def layout_stats(self, mode):
         out = (C.c_int64 * 8)()
