@@ -1,0 +1,85 @@
+/*
+ * vest_serve.h -- request loop of libvest: many VeST factorization jobs of
+ * uneven order, size and rank share one GPU.
+ *
+ * A server owns one device arena of a fixed size and a fixed number of job
+ * slots (one HIP stream each).  Jobs are queued on submission and admitted
+ * in arrival order, later jobs filling in when the head of the queue does not
+ * fit, as soon as a slot is free and the job's device footprint (observed
+ * tensor, model state, marking tables and the vest_init workspace) fits in
+ * the free part of the arena.  An admitted job keeps its state resident; the
+ * loop enqueues one iteration of Alg. 2 (every factor sweep, Alg. 4, then the
+ * core sweep, Eq. 12 / Eq. 14) at a time on the job's stream, so the work of
+ * all admitted jobs overlaps on the device.  A finished job's factors, core
+ * and loss (Eq. 1 / Eq. 2, Eq. 4) are copied to host memory owned by the
+ * server and its device memory returns to the arena.  Every kernel of the
+ * library sums in a fixed order, so a job's result does not depend on what
+ * else runs beside it.
+ *
+ * Threading: a server is driven by one host thread (vest_server_progress is
+ * not re-entrant).  All host pointers of a job must stay valid until the job
+ * has left the QUEUED state.
+ */
+#ifndef VEST_SERVE_H
+#define VEST_SERVE_H
+
+#include "vest.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vest_server vest_server;   /* opaque, library-owned host object */
+
+enum { VEST_JOB_QUEUED = 0, VEST_JOB_ACTIVE = 1, VEST_JOB_DONE = 2, VEST_JOB_FAILED = 3 };
+
+typedef struct {
+    vest_desc desc;                 /* problem, as for vest_init                  */
+    const int32_t *idx;             /* host, nnz*N int32, entry-major             */
+    const double *val;              /* host, nnz FP64                             */
+    const double *const *factors;   /* host array of N host arrays, I_n*J_n FP64,
+                                       initial factors                            */
+    const double *core;             /* host, prod(J_n) FP64, initial core         */
+    int32_t iterations;             /* iterations of Alg. 2 (>= 1), no pruning    */
+    int32_t reserved;               /* must be 0                                  */
+} vest_job;
+
+/* Create a server with an arena of device_bytes (allocated once, on the
+ * current device) and `slots` concurrent jobs (1..256). */
+int vest_server_create(size_t device_bytes, int32_t slots, vest_server **out /* host out */);
+
+/* Queue a job; its arrival time is the time of this call.  VEST_ENOSPC if its
+ * footprint exceeds the whole arena, VEST_EINVAL for a bad descriptor or
+ * iteration count (checked as vest_init does, without touching the data). */
+int vest_server_submit(vest_server *s, const vest_job *job, int64_t *id /* host out */);
+
+/* One scheduling pass: retire jobs whose last iteration has completed,
+ * enqueue the next iteration of every admitted job whose previous one has
+ * completed, admit queued jobs that fit.  Waits for the GPU only inside the
+ * admission (vest_init) and the retirement (result copies) of a job.
+ * *completed (may be NULL) receives the number of jobs retired by this pass. */
+int vest_server_progress(vest_server *s, int32_t *completed);
+
+/* State of a job and its times in seconds since the server was created:
+ * times[0] arrival, times[1] admission, times[2] completion (-1 if not yet).
+ * For a failed job *state is VEST_JOB_FAILED and *error the VEST_E* code. */
+int vest_server_status(vest_server *s, int64_t id, int32_t *state, int32_t *error, double times[3]);
+
+/* Copy a finished job's results to caller memory (any of the pointers may be
+ * NULL) and release them:  factors = host array of N host arrays,
+ * core = prod(J_n) doubles, loss = 5 doubles as vest_loss.  VEST_ESTATE if
+ * the job has not finished (or was fetched already). */
+int vest_server_fetch(vest_server *s, int64_t id, double *const *factors, double *core, double *loss);
+
+/* out[0] queued, out[1] active, out[2] finished (not fetched), out[3] arena
+ * bytes in use, out[4] arena size, out[5] largest free block. */
+int vest_server_stats(vest_server *s, int64_t *out /* 6 values */);
+
+/* Wait for all enqueued work and release everything (unfetched results too). */
+int vest_server_destroy(vest_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VEST_SERVE_H */

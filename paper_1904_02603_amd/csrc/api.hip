@@ -29,7 +29,7 @@ static int device_error(vest_ctx *c, hipError_t e, const char *where)
     return VEST_EDEVICE;
 }
 
-static int check_desc(const vest_desc *d)
+int check_desc(const vest_desc *d)
 {
     if (!d) { set_error("null descriptor"); return VEST_EINVAL; }
     if (d->order < 2 || d->order > VEST_MAX_ORDER) { set_error("order %d outside 2..%d", d->order, VEST_MAX_ORDER); return VEST_EINVAL; }

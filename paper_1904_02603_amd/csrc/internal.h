@@ -212,5 +212,6 @@ struct Bump {
 };
 
 void set_error(const char *fmt, ...);
+int check_desc(const vest_desc *d);   // VEST_OK or the code vest_init would return for the descriptor
 
 }  // namespace vest

@@ -1,0 +1,494 @@
+// Request loop of libvest (include/vest_serve.h): admission by device
+// footprint into one arena, one stream per job slot, one iteration of Alg. 2
+// in flight per admitted job.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "vest_serve.h"
+
+namespace {
+
+using vest::set_error;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing of adjacent free blocks.
+class Arena {
+public:
+    void reset(size_t size)
+    {
+        free_.clear();
+        used_ = 0;
+        size_ = size;
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t n, size_t *off)
+    {
+        n = align_up(n ? n : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n;
+            const size_t start = it->first + n;
+            free_.erase(it);
+            if (rest) free_[start] = rest;
+            used_ += n;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = align_up(n ? n : 1);
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+    size_t largest() const
+    {
+        size_t m = 0;
+        for (auto &f : free_) m = f.second > m ? f.second : m;
+        return m;
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0, size_ = 0;
+};
+
+// One device allocation of a job: offset and size inside the arena.
+struct Block {
+    size_t off = 0, bytes = 0;
+    bool live = false;
+};
+
+struct Job {
+    int64_t id = 0;
+    vest_job in{};
+    int N = 0;
+    int64_t G = 1;
+    int32_t state = VEST_JOB_QUEUED;
+    int32_t error = 0;
+    double t_arrive = -1, t_admit = -1, t_done = -1;
+    size_t ws_bytes = 0;
+    // device blocks: 0 workspace, 1 factors, 2 core, 3 factor masks, 4 core
+    // mask, 5 idx, 6 val (5 and 6 only until vest_init has returned)
+    Block blk[7];
+    vest_ctx *ctx = nullptr;
+    int slot = -1;
+    int32_t iters_done = 0;
+    bool inflight = false;
+    // results (host)
+    std::vector<double> res_fac, res_core;
+    double loss[5] = {0, 0, 0, 0, 0};
+    bool fetched = false;
+
+    size_t fac_elems() const
+    {
+        size_t s = 0;
+        for (int n = 0; n < N; ++n) s += (size_t)in.desc.dims[n] * in.desc.ranks[n];
+        return s;
+    }
+    size_t mask_words() const
+    {
+        size_t s = 0;
+        for (int n = 0; n < N; ++n) s += (size_t)in.desc.dims[n];
+        return s;
+    }
+    size_t block_bytes(int b) const
+    {
+        switch (b) {
+        case 0: return ws_bytes;
+        case 1: return fac_elems() * 8;
+        case 2: return (size_t)G * 8;
+        case 3: return mask_words() * 4;
+        case 4: return (size_t)G;
+        case 5: return (size_t)in.desc.nnz * N * 4;
+        default: return (size_t)in.desc.nnz * 8;
+        }
+    }
+    size_t footprint() const
+    {
+        size_t s = 0;
+        for (int b = 0; b < 7; ++b) s += align_up(block_bytes(b));
+        return s;
+    }
+};
+
+}  // namespace
+
+struct vest_server {
+    char *base = nullptr;
+    Arena arena;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<int64_t> slot_job;   // job id per slot, -1 if free
+    std::map<int64_t, std::unique_ptr<Job>> jobs;
+    std::deque<int64_t> queue;
+    std::vector<int64_t> active;
+    int64_t next_id = 1;
+    int device = 0;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    char *ptr(const Block &b) const { return base + b.off; }
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char *where)
+{
+    set_error("%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+    return VEST_EDEVICE;
+}
+
+void release_blocks(vest_server *s, Job &j)
+{
+    for (auto &b : j.blk)
+        if (b.live) {
+            s->arena.release(b.off, b.bytes);
+            b.live = false;
+        }
+}
+
+// Pointers of a job's blocks in the form vest_init takes.
+struct JobPtrs {
+    double *fac[VEST_MAX_ORDER];
+    uint32_t *fmask[VEST_MAX_ORDER];
+    double *core;
+    uint8_t *cmask;
+};
+
+JobPtrs job_ptrs(vest_server *s, Job &j)
+{
+    JobPtrs p{};
+    double *f = (double *)s->ptr(j.blk[1]);
+    uint32_t *m = (uint32_t *)s->ptr(j.blk[3]);
+    for (int n = 0; n < j.N; ++n) {
+        p.fac[n] = f;
+        p.fmask[n] = m;
+        f += (size_t)j.in.desc.dims[n] * j.in.desc.ranks[n];
+        m += (size_t)j.in.desc.dims[n];
+    }
+    p.core = (double *)s->ptr(j.blk[2]);
+    p.cmask = (uint8_t *)s->ptr(j.blk[4]);
+    return p;
+}
+
+// Allocate, upload and initialise a queued job in slot `slot`.  Returns
+// false (nothing held) if the arena cannot hold it now; on a hard error the
+// job is marked failed.
+bool admit(vest_server *s, Job &j, int slot)
+{
+    for (int b = 0; b < 7; ++b) {
+        j.blk[b].bytes = j.block_bytes(b);
+        if (!s->arena.alloc(j.blk[b].bytes, &j.blk[b].off)) {
+            release_blocks(s, j);
+            return false;
+        }
+        j.blk[b].live = true;
+    }
+    hipStream_t st = s->streams[slot];
+    JobPtrs p = job_ptrs(s, j);
+    const vest_desc &d = j.in.desc;
+    hipError_t e = hipMemcpyAsync(s->ptr(j.blk[5]), j.in.idx, j.blk[5].bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->ptr(j.blk[6]), j.in.val, j.blk[6].bytes, hipMemcpyHostToDevice, st);
+    for (int n = 0; n < j.N && e == hipSuccess; ++n)
+        e = hipMemcpyAsync(p.fac[n], j.in.factors[n], (size_t)d.dims[n] * d.ranks[n] * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p.core, j.in.core, (size_t)j.G * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ptr(j.blk[3]), 0, j.blk[3].bytes, st);
+    if (e == hipSuccess) e = hipMemsetAsync(s->ptr(j.blk[4]), 0, j.blk[4].bytes, st);
+    int rc = e == hipSuccess ? VEST_OK : hip_fail(e, "job upload");
+    if (rc == VEST_OK)
+        rc = vest_init(&d, st, (const int32_t *)s->ptr(j.blk[5]), (const double *)s->ptr(j.blk[6]), p.fac, p.core,
+                       p.fmask, p.cmask, s->ptr(j.blk[0]), j.ws_bytes, &j.ctx);
+    // the observed tensor now lives in the workspace layouts
+    for (int b = 5; b < 7; ++b)
+        if (j.blk[b].live) {
+            s->arena.release(j.blk[b].off, j.blk[b].bytes);
+            j.blk[b].live = false;
+        }
+    j.t_admit = s->now();
+    if (rc != VEST_OK) {
+        hipStreamSynchronize(st);
+        release_blocks(s, j);
+        j.state = VEST_JOB_FAILED;
+        j.error = rc;
+        j.t_done = s->now();
+        return true;
+    }
+    j.slot = slot;
+    s->slot_job[slot] = j.id;
+    j.state = VEST_JOB_ACTIVE;
+    return true;
+}
+
+int enqueue_iteration(vest_server *s, Job &j)
+{
+    int rc = VEST_OK;
+    for (int n = 0; n < j.N && rc == VEST_OK; ++n) rc = vest_sweep_factor(j.ctx, n);
+    if (rc == VEST_OK) rc = vest_sweep_core(j.ctx);
+    if (rc != VEST_OK) return rc;
+    hipError_t e = hipEventRecord(s->events[j.slot], s->streams[j.slot]);
+    if (e != hipSuccess) return hip_fail(e, "event record");
+    j.inflight = true;
+    return VEST_OK;
+}
+
+// Loss, result copies, release.  Synchronises the job's stream.
+void retire(vest_server *s, Job &j)
+{
+    hipStream_t st = s->streams[j.slot];
+    int rc = vest_loss(j.ctx, j.loss);
+    if (rc == VEST_OK) {
+        JobPtrs p = job_ptrs(s, j);
+        j.res_fac.resize(j.fac_elems());
+        j.res_core.resize((size_t)j.G);
+        hipError_t e = hipMemcpyAsync(j.res_fac.data(), p.fac[0], j.res_fac.size() * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(j.res_core.data(), p.core, j.res_core.size() * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "result copy");
+    }
+    vest_destroy(j.ctx);
+    j.ctx = nullptr;
+    release_blocks(s, j);
+    s->slot_job[j.slot] = -1;
+    j.slot = -1;
+    j.state = rc == VEST_OK ? VEST_JOB_DONE : VEST_JOB_FAILED;
+    j.error = rc;
+    j.t_done = s->now();
+}
+
+}  // namespace
+
+extern "C" {
+
+int vest_server_create(size_t device_bytes, int32_t slots, vest_server **out)
+{
+    if (!out || slots < 1 || slots > 256 || device_bytes < kAlign) {
+        set_error("bad server arguments (slots %d, %zu bytes)", slots, device_bytes);
+        return VEST_EINVAL;
+    }
+    vest_server *s = new (std::nothrow) vest_server();
+    if (!s) { set_error("out of host memory"); return VEST_EINVAL; }
+    s->t0 = std::chrono::steady_clock::now();
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->base, device_bytes);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "server arena");
+    }
+    s->arena.reset(device_bytes / kAlign * kAlign);
+    s->streams.assign(slots, nullptr);
+    s->events.assign(slots, nullptr);
+    s->slot_job.assign(slots, -1);
+    for (int i = 0; i < slots && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        vest_server_destroy(s);
+        return hip_fail(e, "server streams");
+    }
+    *out = s;
+    return VEST_OK;
+}
+
+int vest_server_submit(vest_server *s, const vest_job *job, int64_t *id)
+{
+    if (!s || !job || !id) { set_error("null argument"); return VEST_EINVAL; }
+    int rc = vest::check_desc(&job->desc);
+    if (rc) return rc;
+    if (job->iterations < 1 || job->reserved != 0) { set_error("iterations must be >= 1, reserved 0"); return VEST_EINVAL; }
+    if (!job->idx || !job->val || !job->factors || !job->core) { set_error("null job array"); return VEST_EINVAL; }
+    for (int n = 0; n < job->desc.order; ++n)
+        if (!job->factors[n]) { set_error("null factor %d", n); return VEST_EINVAL; }
+    std::unique_ptr<Job> j(new (std::nothrow) Job());
+    if (!j) { set_error("out of host memory"); return VEST_EINVAL; }
+    j->in = *job;
+    j->N = job->desc.order;
+    for (int n = 0; n < j->N; ++n) j->G *= job->desc.ranks[n];
+    rc = vest_workspace_bytes(&job->desc, &j->ws_bytes);
+    if (rc) return rc;
+    if (j->footprint() > s->arena.size()) {
+        set_error("job footprint %zu bytes exceeds the arena of %zu", j->footprint(), s->arena.size());
+        return VEST_ENOSPC;
+    }
+    j->id = s->next_id++;
+    j->t_arrive = s->now();
+    *id = j->id;
+    s->queue.push_back(j->id);
+    s->jobs[j->id] = std::move(j);
+    return VEST_OK;
+}
+
+int vest_server_progress(vest_server *s, int32_t *completed)
+{
+    if (!s) { set_error("null server"); return VEST_EINVAL; }
+    int32_t done = 0;
+    // 1. advance admitted jobs
+    std::vector<int64_t> still;
+    for (int64_t id : s->active) {
+        Job &j = *s->jobs[id];
+        if (j.inflight) {
+            hipError_t q = hipEventQuery(s->events[j.slot]);
+            if (q == hipErrorNotReady) {
+                still.push_back(id);
+                continue;
+            }
+            if (q != hipSuccess) return hip_fail(q, "event query");
+            j.inflight = false;
+            ++j.iters_done;
+        }
+        if (j.iters_done < j.in.iterations) {
+            int rc = enqueue_iteration(s, j);
+            if (rc != VEST_OK) {
+                retire(s, j);
+                j.state = VEST_JOB_FAILED;
+                j.error = rc;
+                ++done;
+                continue;
+            }
+            still.push_back(id);
+        } else {
+            retire(s, j);
+            ++done;
+        }
+    }
+    s->active.swap(still);
+    // 2. admit queued jobs in arrival order; later jobs fill in when the head
+    //    does not fit yet
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+        int slot = -1;
+        for (size_t k = 0; k < s->slot_job.size(); ++k)
+            if (s->slot_job[k] < 0) { slot = (int)k; break; }
+        if (slot < 0) break;
+        Job &j = *s->jobs[*it];
+        if (j.footprint() > s->arena.size() - s->arena.used()) {
+            ++it;
+            continue;
+        }
+        if (!admit(s, j, slot)) {
+            ++it;
+            continue;
+        }
+        if (j.state == VEST_JOB_ACTIVE) {
+            int rc = enqueue_iteration(s, j);
+            if (rc != VEST_OK) {
+                retire(s, j);
+                j.state = VEST_JOB_FAILED;
+                j.error = rc;
+                ++done;
+            } else {
+                s->active.push_back(j.id);
+            }
+        } else {
+            ++done;  // failed at admission
+        }
+        it = s->queue.erase(it);
+    }
+    if (completed) *completed = done;
+    return VEST_OK;
+}
+
+int vest_server_status(vest_server *s, int64_t id, int32_t *state, int32_t *error, double *times)
+{
+    if (!s) { set_error("null server"); return VEST_EINVAL; }
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) { set_error("unknown job %lld", (long long)id); return VEST_EINVAL; }
+    const Job &j = *it->second;
+    if (state) *state = j.state;
+    if (error) *error = j.error;
+    if (times) {
+        times[0] = j.t_arrive;
+        times[1] = j.t_admit;
+        times[2] = j.t_done;
+    }
+    return VEST_OK;
+}
+
+int vest_server_fetch(vest_server *s, int64_t id, double *const *factors, double *core, double *loss)
+{
+    if (!s) { set_error("null server"); return VEST_EINVAL; }
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) { set_error("unknown job %lld", (long long)id); return VEST_EINVAL; }
+    Job &j = *it->second;
+    if (j.state != VEST_JOB_DONE || j.fetched) { set_error("job %lld has no results to fetch", (long long)id); return VEST_ESTATE; }
+    if (factors) {
+        size_t off = 0;
+        for (int n = 0; n < j.N; ++n) {
+            const size_t len = (size_t)j.in.desc.dims[n] * j.in.desc.ranks[n];
+            if (factors[n]) std::memcpy(factors[n], j.res_fac.data() + off, len * 8);
+            off += len;
+        }
+    }
+    if (core) std::memcpy(core, j.res_core.data(), j.res_core.size() * 8);
+    if (loss) std::memcpy(loss, j.loss, sizeof(j.loss));
+    j.fetched = true;
+    std::vector<double>().swap(j.res_fac);
+    std::vector<double>().swap(j.res_core);
+    return VEST_OK;
+}
+
+int vest_server_stats(vest_server *s, int64_t *out)
+{
+    if (!s || !out) { set_error("null argument"); return VEST_EINVAL; }
+    int64_t finished = 0;
+    for (auto &kv : s->jobs)
+        if (kv.second->state == VEST_JOB_DONE && !kv.second->fetched) ++finished;
+    out[0] = (int64_t)s->queue.size();
+    out[1] = (int64_t)s->active.size();
+    out[2] = finished;
+    out[3] = (int64_t)s->arena.used();
+    out[4] = (int64_t)s->arena.size();
+    out[5] = (int64_t)s->arena.largest();
+    return VEST_OK;
+}
+
+int vest_server_destroy(vest_server *s)
+{
+    if (!s) return VEST_OK;
+    for (hipStream_t st : s->streams)
+        if (st) hipStreamSynchronize(st);
+    for (int64_t id : s->active) {
+        Job &j = *s->jobs[id];
+        if (j.ctx) vest_destroy(j.ctx);
+        j.ctx = nullptr;
+    }
+    for (hipEvent_t ev : s->events)
+        if (ev) hipEventDestroy(ev);
+    for (hipStream_t st : s->streams)
+        if (st) hipStreamDestroy(st);
+    if (s->base) hipFree(s->base);
+    delete s;
+    return VEST_OK;
+}
+
+}  // extern "C"

@@ -8,6 +8,7 @@ machine where it is missing raises immediately -- there is no fallback.
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -21,7 +22,10 @@ KERNEL_AUTO, KERNEL_DENSE, KERNEL_GATHER = 0, 1, 2
 
 EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
            "vest_responsibility", "vest_prune", "vest_loss", "vest_set_kernel", "vest_layout_stats",
-           "vest_destroy", "vest_strerror", "vest_last_error"]
+           "vest_destroy", "vest_strerror", "vest_last_error",
+           "vest_server_create", "vest_server_submit", "vest_server_progress", "vest_server_status",
+           "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]
+JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 
 class VestError(RuntimeError):
@@ -70,6 +74,16 @@ def load_library(path=LIB_PATH):
     lib.vest_strerror.restype = C.c_char_p
     lib.vest_last_error.argtypes = []
     lib.vest_last_error.restype = C.c_char_p
+    lib.vest_server_create.argtypes = [C.c_size_t, i32, C.POINTER(vp)]
+    lib.vest_server_submit.argtypes = [vp, C.POINTER(Job), C.POINTER(i64)]
+    lib.vest_server_progress.argtypes = [vp, C.POINTER(i32)]
+    lib.vest_server_status.argtypes = [vp, i64, C.POINTER(i32), C.POINTER(i32), vp]
+    lib.vest_server_fetch.argtypes = [vp, i64, vp, vp, vp]
+    lib.vest_server_stats.argtypes = [vp, vp]
+    lib.vest_server_destroy.argtypes = [vp]
+    for name in ["vest_server_create", "vest_server_submit", "vest_server_progress", "vest_server_status",
+                 "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]:
+        getattr(lib, name).restype = C.c_int
     for name in ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
                  "vest_responsibility", "vest_prune", "vest_loss", "vest_set_kernel", "vest_layout_stats",
                  "vest_destroy"]:
@@ -221,6 +235,96 @@ class VestContext:
         if self.ctx is not None and self.ctx.value:
             self.lib.vest_destroy(self.ctx)
             self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def job_footprint(dims, ranks, nnz, reg=REG_LF, lam=0.01, precision=FP32):
+    """Device bytes a server reserves to admit a job (see vest_serve.h)."""
+    def a(x):
+        return (int(x) + 255) // 256 * 256
+    N = len(dims)
+    G = int(np.prod(ranks))
+    ws = workspace_bytes(dims, ranks, nnz, reg, lam, precision)
+    return (a(ws) + a(sum(I * J for I, J in zip(dims, ranks)) * 8) + a(G * 8) + a(sum(dims) * 4) + a(G)
+            + a(nnz * N * 4) + a(nnz * 8))
+
+
+class Job(C.Structure):
+    """vest_job of vest_serve.h."""
+    _fields_ = [("desc", Desc), ("idx", C.c_void_p), ("val", C.c_void_p), ("factors", C.c_void_p),
+                ("core", C.c_void_p), ("iterations", C.c_int32), ("reserved", C.c_int32)]
+
+
+class VestServer:
+    """Request loop of vest_serve.h: jobs share one device arena of
+    `device_bytes` and `slots` streams; see the header for the policy."""
+
+    def __init__(self, device_bytes, slots):
+        self.lib = load_library()
+        self.srv = C.c_void_p()
+        _check(self.lib.vest_server_create(int(device_bytes), int(slots), C.byref(self.srv)), "vest_server_create")
+        self._keep = {}
+        self._shape = {}
+
+    def submit(self, idx, val, factors, core, reg=REG_LF, lam=0.01, precision=FP32, iterations=10):
+        """Queue a job (numpy host arrays); returns its id."""
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        factors = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+        core = np.ascontiguousarray(core, dtype=np.float64)
+        dims = [f.shape[0] for f in factors]
+        ranks = [f.shape[1] for f in factors]
+        fp = (C.c_void_p * len(factors))(*[f.ctypes.data for f in factors])
+        j = Job()
+        j.desc = make_desc(dims, ranks, idx.shape[0], reg, lam, precision)
+        j.idx, j.val, j.factors, j.core = idx.ctypes.data, val.ctypes.data, C.cast(fp, C.c_void_p), core.ctypes.data
+        j.iterations = int(iterations)
+        j.reserved = 0
+        jid = C.c_int64(0)
+        _check(self.lib.vest_server_submit(self.srv, C.byref(j), C.byref(jid)), "vest_server_submit")
+        self._keep[jid.value] = (idx, val, factors, core, fp, j)
+        self._shape[jid.value] = (dims, ranks)
+        return jid.value
+
+    def progress(self):
+        """One scheduling pass; returns the number of jobs retired by it."""
+        done = C.c_int32(0)
+        _check(self.lib.vest_server_progress(self.srv, C.byref(done)), "vest_server_progress")
+        return done.value
+
+    def status(self, jid):
+        st, err = C.c_int32(0), C.c_int32(0)
+        t = (C.c_double * 3)()
+        _check(self.lib.vest_server_status(self.srv, int(jid), C.byref(st), C.byref(err), t), "vest_server_status")
+        if st.value != JOB_QUEUED:
+            self._keep.pop(jid, None)  # inputs were read at admission
+        return {"state": st.value, "error": err.value, "arrive": t[0], "admit": t[1], "done": t[2]}
+
+    def fetch(self, jid):
+        """Factors (list of numpy [I_n, J]), core and loss dict of a finished job."""
+        dims, ranks = self._shape[jid]
+        fac = [np.empty((I, J)) for I, J in zip(dims, ranks)]
+        core = np.empty(tuple(ranks))
+        loss = (C.c_double * 5)()
+        fp = (C.c_void_p * len(fac))(*[f.ctypes.data for f in fac])
+        _check(self.lib.vest_server_fetch(self.srv, int(jid), fp, core.ctypes.data, loss), "vest_server_fetch")
+        return fac, core, dict(zip(["sse", "xnorm2", "reg", "loss", "re"], list(loss)))
+
+    def stats(self):
+        out = (C.c_int64 * 6)()
+        _check(self.lib.vest_server_stats(self.srv, out), "vest_server_stats")
+        return dict(zip(["queued", "active", "finished", "bytes_used", "bytes_total", "largest_free"], list(out)))
+
+    def close(self):
+        if self.srv is not None and self.srv.value:
+            self.lib.vest_server_destroy(self.srv)
+            self.srv = C.c_void_p()
+        self._keep.clear()
 
     def __del__(self):
         try:

@@ -7,11 +7,12 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "vest.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("vest.h", "vest_serve.h")]
 LIB = os.path.join(ROOT, "paper_1904_02603_amd", "libvest.so")
 
 
 def declared():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(vest_[a-z_]+)\s*\(", src)))
 

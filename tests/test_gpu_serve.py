@@ -1,0 +1,127 @@
+"""GPU checks of the request loop (vest_serve.h).
+
+Jobs of different order, rank, regulariser and precision run through one
+server with fewer slots than jobs, so some wait and the admitted ones overlap
+on the device; each result must equal bit for bit the same job run alone
+through the plain context (every kernel sums in a fixed order, so the mix
+cannot change a result).  The arena bound, the rejection of a job larger than
+the arena and the failure of a job with invalid data are checked as well.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1904_02603_amd import synth
+from test_gpu_parity import V, say
+
+pytestmark = pytest.mark.gpu
+
+JOBS = [
+    # dims, ranks, nnz, zipf, reg, lam, precision
+    ((100, 80, 60), 5, 5000, None, 0, 0.05, "FP32"),
+    ((300, 200, 100), 10, 30_000, None, 1, 0.5, "BF16"),
+    ((30, 25, 20, 24), 8, 5000, None, 0, 0.05, "FP32"),
+    ((2000, 300, 50), 4, 30_000, (1.1, 1.0, None), 1, 0.5, "FP64"),
+    ((40, 50, 30), 3, 2000, None, 0, 0.05, "BF16"),
+    ((12, 10, 8, 9), 3, 3000, None, 0, 0.1, "FP64"),
+]
+
+
+def job_inputs(k):
+    dims, J, nnz, zipf, reg, lam, prec = JOBS[k]
+    p = synth.make_problem(dims, nnz, (J,) * len(dims), 60 + k, zipf=zipf, noise_var=0.01)
+    return p, reg, lam, getattr(V(), prec)
+
+
+def drain(srv, ids, limit_s=120.0):
+    t0 = time.time()
+    peak = {"active": 0, "bytes": 0}
+    while True:
+        srv.progress()
+        st = srv.stats()
+        peak["active"] = max(peak["active"], st["active"])
+        peak["bytes"] = max(peak["bytes"], st["bytes_used"])
+        assert st["bytes_used"] <= st["bytes_total"]
+        if all(srv.status(i)["state"] >= V().JOB_DONE for i in ids):
+            return peak
+        assert time.time() - t0 < limit_s, "server did not finish"
+        time.sleep(0.0005)
+
+
+def alone(p, reg, lam, prec, iters):
+    ctx = V().VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec)
+    for _ in range(iters):
+        ctx.iteration()
+    L = ctx.loss()
+    torch.cuda.synchronize()
+    out = ([f.cpu().numpy().copy() for f in ctx.factors], ctx.core.cpu().numpy().copy(), L)
+    ctx.close()
+    return out
+
+
+def test_results_in_the_mix_equal_results_alone():
+    v = V()
+    iters = 3
+    srv = v.VestServer(1 << 30, 3)
+    ins = [job_inputs(k) for k in range(len(JOBS))]
+    ids = [srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec,
+                      iterations=iters) for p, reg, lam, prec in ins]
+    peak = drain(srv, ids)
+    say("peak active", peak["active"])
+    assert peak["active"] >= 2  # jobs overlapped
+    for k, (jid, (p, reg, lam, prec)) in enumerate(zip(ids, ins)):
+        st = srv.status(jid)
+        assert st["state"] == v.JOB_DONE, (k, st)
+        assert st["arrive"] <= st["admit"] <= st["done"]
+        fac, core, loss = srv.fetch(jid)
+        afac, acore, aloss = alone(p, reg, lam, prec, iters)
+        for n in range(len(fac)):
+            assert np.array_equal(fac[n], afac[n]), (k, n)
+        assert np.array_equal(core, acore), k
+        assert loss["loss"] == aloss["loss"] and loss["re"] == aloss["re"], k
+    srv.close()
+
+
+def test_admission_keeps_the_arena_bound():
+    v = V()
+    p, reg, lam, prec = job_inputs(1)
+    dims = [f.shape[0] for f in p["factors"]]
+    fp = v.job_footprint(dims, [10] * 3, p["idx"].shape[0], reg, lam, prec)
+    srv = v.VestServer(int(2.5 * fp), 8)   # room for two jobs at a time
+    ids = [srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec,
+                      iterations=2) for _ in range(5)]
+    peak = drain(srv, ids)
+    say("footprint", fp, "peak active", peak["active"], "peak bytes", peak["bytes"])
+    assert peak["active"] <= 2
+    res = [srv.fetch(i) for i in ids]
+    for f, c, L in res[1:]:
+        assert np.array_equal(c, res[0][1]) and L["loss"] == res[0][2]["loss"]
+    srv.close()
+
+
+def test_oversized_and_invalid_jobs():
+    v = V()
+    p, reg, lam, prec = job_inputs(4)
+    dims = [f.shape[0] for f in p["factors"]]
+    fp = v.job_footprint(dims, [3] * 3, p["idx"].shape[0], reg, lam, prec)
+    srv = v.VestServer(fp // 2, 2)
+    with pytest.raises(v.VestError) as ei:
+        srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec)
+    assert ei.value.code == v.ENOSPC
+    srv.close()
+    srv = v.VestServer(4 * fp, 2)
+    bad = p["idx"].copy()
+    bad[1] = bad[0]  # duplicate index tuple
+    jb = srv.submit(bad, p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec, iterations=1)
+    jg = srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec, iterations=1)
+    drain(srv, [jb, jg])
+    assert srv.status(jb)["state"] == v.JOB_FAILED and srv.status(jb)["error"] == v.EINVAL
+    assert srv.status(jg)["state"] == v.JOB_DONE
+    with pytest.raises(v.VestError) as ei:
+        srv.fetch(jb)
+    assert ei.value.code == v.ESTATE
+    srv.fetch(jg)
+    assert srv.stats()["bytes_used"] == 0
+    srv.close()
