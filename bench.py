@@ -29,6 +29,7 @@ DEFAULT_WORKLOAD = "planted-1e5^3-nnz1e7-r10"
 METRIC = "observed-entry CD updates/sec per sweep (FP64 vs FP32/BF16) + p99 job latency"
 PEAK = {"f64": 78.6, "f32": 157.3}        # TFLOP/s, MI355X vector FP64 / FP32
 HBM_PEAK = 8000.0                          # GB/s
+SERVE_SEED = 20190407
 
 
 def log(*a):
@@ -184,6 +185,79 @@ def sparse_phase(p, frac, steps, precision):
     return out
 
 
+def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
+    """Serving stream: a pool of observed tensors and n_jobs jobs over it
+    (synth.serving_jobs); a serial pass of the first `calib` jobs (one slot,
+    all submitted at once) gives the serial rate; then the jobs arrive as a
+    Poisson stream at 0.8 x that rate and run through one server with `slots`
+    slots and an arena of arena_bytes.  Latency = completion - arrival, both
+    taken by the server."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1904_02603_amd import synth, vest
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        tensors = list(ex.map(synth.serving_tensor, range(pool)))
+    jobs = synth.serving_jobs(n_jobs, tensors)
+    log("  pool of %d tensors (%.1f M entries) in %.1f s" % (
+        pool, sum(t["idx"].shape[0] for t in tensors) / 1e6, time.perf_counter() - t0))
+
+    def submit(srv, j):
+        t = tensors[j["tensor"]]
+        fac, core = synth.serving_init(j, t["dims"])
+        return srv.submit(t["idx"], t["val"], fac, core, reg=j["reg"], lam=j["lam"],
+                          precision=getattr(vest, j["form"]), iterations=j["iterations"])
+
+    def run(srv, arrivals):
+        start = time.perf_counter()
+        ids, i, retired = [], 0, 0
+        while retired < len(arrivals):
+            now = time.perf_counter() - start
+            while i < len(arrivals) and arrivals[i] <= now:
+                ids.append(submit(srv, jobs[i]))
+                i += 1
+            got = srv.progress()
+            retired += got
+            if got == 0:
+                time.sleep(0.0002)
+        recs = []
+        for jid in ids:
+            st = srv.status(jid)
+            if st["state"] != vest.JOB_DONE:
+                raise RuntimeError("serving job %d failed: %s" % (jid, st))
+            srv.fetch(jid)
+            recs.append((st["arrive"], st["admit"], st["done"]))
+        return np.array(recs)
+
+    srv = vest.VestServer(arena_bytes, 1)
+    r = run(srv, np.zeros(calib))
+    srv.close()
+    serial_rate = calib / (r[:, 2].max() - r[:, 0].min())
+    rate = 0.8 * serial_rate
+    arrivals = np.cumsum(np.random.default_rng(SERVE_SEED).exponential(1.0 / rate, n_jobs))
+    srv = vest.VestServer(arena_bytes, slots)
+    r = run(srv, arrivals)
+    srv.close()
+    # saturated: the whole stream queued at once (capacity of the server)
+    srv = vest.VestServer(arena_bytes, slots)
+    rs = run(srv, np.zeros(n_jobs))
+    srv.close()
+    sat_rate = n_jobs / (rs[:, 2].max() - rs[:, 0].min())
+    lat = r[:, 2] - r[:, 0]
+    wait = r[:, 1] - r[:, 0]
+    span = r[:, 2].max() - r[:, 0].min()
+    forms = {f: sum(1 for j in jobs if j["form"] == f) for f in ("FP32", "BF16")}
+    return {"jobs": n_jobs, "jobs_per_s": n_jobs / span, "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)), "latency_mean_s": float(lat.mean()),
+            "admission_wait_p99_s": float(np.percentile(wait, 99)),
+            "saturated_jobs_per_s": sat_rate, "serial_jobs_per_s": serial_rate, "serial_calibration_jobs": calib, "arrival_rate_per_s": rate,
+            "slots": slots, "arena_bytes": arena_bytes, "pool_tensors": pool,
+            "pool_entries": int(sum(t["idx"].shape[0] for t in tensors)),
+            "job_entries_total": int(sum(tensors[j["tensor"]]["idx"].shape[0] for j in jobs)),
+            "forms": forms, "orders": {str(o): sum(1 for j in jobs if len(j["ranks"]) == o) for o in (3, 4)},
+            "iterations_per_job": 10}
+
+
 def measured_traffic():
     """Calibrated HBM bytes per launch of the factor-sweep kernel from the
     committed counter summary, or None if the kernel changed since."""
@@ -243,6 +317,11 @@ def main():
     ap.add_argument("--accuracy-iters", type=int, default=5)
     ap.add_argument("--sparse-frac", type=float, default=0.95,
                     help="marked fraction of the pruned-phase sweep section (0 = skip it)")
+    ap.add_argument("--serve-jobs", type=int, default=512, help="serving stream length (0 = skip)")
+    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-arena-gb", type=float, default=32.0)
+    ap.add_argument("--serve-calib", type=int, default=32)
     ap.add_argument("--legs", default="fp64,fp32,bf16",
                     help="comma list of forms to time (the first must be fp64 for a bench line)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -302,6 +381,13 @@ def main():
                                         {"fp64": vest.FP64, "fp32": vest.FP32, "bf16": vest.BF16}[name])
             log("  dense %.3f ms, gather %.3f ms per sweep" % (sparse[name]["dense_ms_per_sweep"],
                                                             sparse[name]["gather_ms_per_sweep"]))
+    serving = None
+    if args.serve_jobs > 0:
+        log("serving stream (%d jobs) ..." % args.serve_jobs)
+        serving = serving_bench(args.serve_jobs, args.serve_pool, int(args.serve_arena_gb * (1 << 30)),
+                                args.serve_slots, min(args.serve_calib, args.serve_jobs))
+        log("  %.2f jobs/s, p50 %.3f s, p99 %.3f s (serial %.2f jobs/s)" % (
+            serving["jobs_per_s"], serving["latency_p50_s"], serving["latency_p99_s"], serving["serial_jobs_per_s"]))
     cpu = None
     if args.cpu_seconds > 0:
         log("oracle CPU baseline ...")
@@ -346,6 +432,8 @@ def main():
         out["accuracy_dense"] = acc
     if sparse:
         out["pruned_phase"] = sparse
+    if serving is not None:
+        out["serving"] = serving
     if args.nnz is not None:
         out["config"]["note"] = "reduced nnz: not the named workload"
     print(json.dumps(out))

@@ -53,21 +53,39 @@ def observed_indices(dims, nnz, rng, zipf=None):
     samplers = [(_zipf_sampler(dims[n], zipf[n], rng) if zipf[n] else _uniform_sampler(dims[n], rng))
                 for n in range(N)]
     linear = total < 2 ** 62
-    got = np.empty((0, N), dtype=np.int64)
-    while got.shape[0] < nnz:
-        need = nnz - got.shape[0]
-        draw = int(need * 1.05) + 64
-        cand = np.stack([samplers[n](draw) for n in range(N)], axis=1).astype(np.int64)
-        allt = np.concatenate([got, cand], axis=0)
-        if linear:
-            key = np.zeros(allt.shape[0], dtype=np.int64)
+    if linear:
+        # rounds of draws; a round keeps its first occurrences that are not
+        # already taken, in draw order (taken keys kept sorted for lookup)
+        parts, taken, count = [], np.empty(0, dtype=np.int64), 0
+        while count < nnz:
+            need = nnz - count
+            draw = int(need * 1.05) + 64
+            cand = np.stack([samplers[n](draw) for n in range(N)], axis=1).astype(np.int64)
+            key = np.zeros(draw, dtype=np.int64)
             for n in range(N):
-                key = key * int(dims[n]) + allt[:, n]
+                key = key * int(dims[n]) + cand[:, n]
             _, first = np.unique(key, return_index=True)
-        else:
+            first.sort()
+            kc = key[first]
+            pos = np.searchsorted(taken, kc)
+            seen = (pos < taken.shape[0]) & (taken[np.minimum(pos, max(taken.shape[0] - 1, 0))] == kc) \
+                if taken.shape[0] else np.zeros(kc.shape[0], dtype=bool)
+            new = first[~seen][:need]
+            parts.append(cand[new])
+            count += new.shape[0]
+            tk = np.sort(key[new])
+            taken = np.insert(taken, np.searchsorted(taken, tk), tk)
+        got = np.concatenate(parts, axis=0)
+    else:
+        got = np.empty((0, N), dtype=np.int64)
+        while got.shape[0] < nnz:
+            need = nnz - got.shape[0]
+            draw = int(need * 1.05) + 64
+            cand = np.stack([samplers[n](draw) for n in range(N)], axis=1).astype(np.int64)
+            allt = np.concatenate([got, cand], axis=0)
             _, first = np.unique(allt, axis=0, return_index=True)
-        first.sort()
-        got = allt[first][:nnz]
+            first.sort()
+            got = allt[first][:nnz]
     return np.ascontiguousarray(got, dtype=np.int32)
 
 
@@ -148,6 +166,65 @@ WORKLOADS = {
                                                  ranks=(8, 8, 8, 8), zipf=(1.1, 1.0, None, None),
                                                  snr_db=20.0, reg=0, lam=0.01, seed=SEED_BASE + 4),
 }
+
+
+# Serving workload: ranks with a compiled kernel instance in 4..10 per order.
+SERVING_RANKS = {3: (4, 5, 6, 8, 10), 4: (4, 5, 6, 8)}
+
+
+def rating_values(idx, dims, rng):
+    """Cheap rating-shaped values for the serving stream: integers 1..5 from
+    clip(rint(3 + 1.25 z)), z = sum of per-mode N(0, 1/N) effects of the entry's
+    indices plus N(0, 0.25) noise (O(nnz N) to draw, unlike a planted Tucker
+    model)."""
+    N = len(dims)
+    z = rng.standard_normal(idx.shape[0]) * 0.5
+    for n in range(N):
+        eff = rng.standard_normal(int(dims[n])) / math.sqrt(N)
+        z += eff[idx[:, n]]
+    return np.clip(np.rint(3.0 + 1.25 * z), 1.0, 5.0)
+
+
+def serving_tensor(k, seed=SEED_BASE + 5, max_nnz=10_000_000):
+    """Observed tensor k of the serving pool (own seeded generator, so the
+    pool can be drawn in parallel): order 3 or 4 with equal probability,
+    every dim log-uniform in [1e3, 1e5], nnz log-uniform in [1e4, max_nnz]
+    capped at half the cells, first two modes bounded Zipf 1.0 and the others
+    uniform, rating values (rating_values)."""
+    rng = np.random.Generator(np.random.PCG64([seed, k]))
+    N = 3 if rng.random() < 0.5 else 4
+    dims = [int(round(10 ** rng.uniform(3, 5))) for _ in range(N)]
+    cells = 1
+    for d in dims:
+        cells *= d
+    nnz = int(round(10 ** rng.uniform(4, math.log10(max_nnz))))
+    nnz = max(1, min(nnz, cells // 2))
+    idx = observed_indices(dims, nnz, rng, [1.0, 1.0] + [None] * (N - 2))
+    return {"idx": idx, "val": rating_values(idx, dims, rng), "dims": dims}
+
+
+def serving_jobs(n_jobs, tensors, seed=SEED_BASE + 6):
+    """Parameters of the serving job stream over a pool of tensors: each job
+    draws a tensor, ranks uniform over SERVING_RANKS[N], L_F / L_1 with equal
+    probability (lambda 0.01 / 0.1), FP32 / BF16 form with equal
+    probability, 10 iterations, and a seed for its U[0, 1) initial state
+    (serving_init)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for i in range(n_jobs):
+        k = int(rng.integers(0, len(tensors)))
+        N = len(tensors[k]["dims"])
+        J = int(rng.choice(SERVING_RANKS[N]))
+        reg = int(rng.integers(0, 2))
+        jobs.append({"tensor": k, "ranks": (J,) * N, "reg": reg, "lam": 0.01 if reg == 0 else 0.1,
+                     "form": "FP32" if rng.random() < 0.5 else "BF16", "iterations": 10,
+                     "init_seed": (seed, i)})
+    return jobs
+
+
+def serving_init(job, dims):
+    """U[0, 1) initial factors and core of a serving job."""
+    return initial_state(dims, job["ranks"], np.random.Generator(np.random.PCG64(list(job["init_seed"]))))
 
 
 def workload(name, nnz=None, dims=None):
