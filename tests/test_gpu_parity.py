@@ -75,8 +75,9 @@ SHAPES = [
     ((30, 25, 20, 24), (8, 8, 8, 8), 5000, None),
     ((60, 70), (3, 3), 1500, None),
     ((2000, 300, 50), (4, 4, 4), 30_000, (1.1, 1.0, None)),
+    ((25, 20, 30, 16), (5, 5, 5, 5), 4000, None),
 ]
-IDS = ["N3J3", "N3J5", "N3J10", "N4J2", "N4J8", "N2J3", "zipfN3J4"]
+IDS = ["N3J3", "N3J5", "N3J10", "N4J2", "N4J8", "N2J3", "zipfN3J4", "N4J5"]
 
 
 @pytest.mark.parametrize("reg", [REG_LF, REG_L1], ids=["LF", "L1"])
