@@ -123,23 +123,23 @@ __device__ __forceinline__ void gather_level(const T *__restrict__ Gt, const uin
     }
 }
 
-// delta of one entry in the gather form.  The marking tables of the other
-// modes (one 32-bit word per row, small enough to stay in L2) are read
-// first; the factor rows are fetched only when every other-mode row still
-// has an unmarked element, otherwise delta = 0 without touching them.
+// delta of one entry in the gather form, given the unmarked-element bits
+// m[k] of its other-mode rows (from the marking tables, one 32-bit word per
+// row, small enough to stay in L2): the factor rows are fetched only when
+// every other-mode row still has an unmarked element, otherwise delta = 0
+// without touching them.
 template <int N, int J, typename T>
 __device__ __forceinline__ void delta_gather(const T *__restrict__ Gt, const uint32_t *__restrict__ Gnz,
-                                             const T *const (&fac)[N - 1], const uint32_t *const (&omask)[N - 1],
-                                             const int32_t (&ii)[N - 1], T (&r)[N - 1][J], T (&d)[J])
+                                             const T *const (&fac)[N - 1], const int32_t (&ii)[N - 1],
+                                             const uint32_t (&mk)[N - 1], T (&r)[N - 1][J], T (&d)[J])
 {
-    constexpr uint32_t full = J == 32 ? 0xffffffffu : (1u << J) - 1u;
 #pragma unroll
     for (int j = 0; j < J; ++j) d[j] = T(0);
     uint32_t m[N - 1];
     bool live = true;
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
-        m[k] = ~omask[k][ii[k]] & full;
+        m[k] = mk[k];
         live = live && m[k] != 0u;
     }
     if (!live) return;
@@ -212,62 +212,86 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
+    // Software pipeline: the indices and value of step k + 1 are loaded at
+    // the top of step k and, in the gather form, the marking words of step
+    // k + 1 before the row statistics of step k, so a step waits for one
+    // memory latency (its factor rows) instead of a chain of two or three.
+    // The prefetch of the last step re-reads that step (in range).
+    constexpr uint32_t full = J == 32 ? 0xffffffffu : (1u << J) - 1u;
     const int K = wi.K;
+    int32_t ci[N - 1];
+    T cx = T(0);
+    auto load_step = [&](int k, int32_t (&ii)[N - 1], T &x) {
+        const int64_t sl = wi.base + (int64_t)k * kWave + lane;
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) ii[m] = a.oidx[m][sl];
+        x = a.xval[sl];
+    };
+    auto load_marks = [&](const int32_t (&ii)[N - 1], uint32_t (&mm)[N - 1]) {
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) mm[m] = ii[0] >= 0 ? (~a.omask[m][ii[m]] & full) : 0u;
+    };
+    if (K > 0) load_step(0, ci, cx);
+#pragma unroll 1
     for (int k = 0; k < K; ++k) {
         const int64_t sl = wi.base + (int64_t)k * kWave + lane;
-        const int32_t i0 = a.oidx[0][sl];
-        if (i0 < 0) {
+        int32_t ni[N - 1];
+        T nx;
+        load_step(k + 1 < K ? k + 1 : k, ni, nx);
+        if (ci[0] < 0) {
             if constexpr (OP == OP_RESID) {
                 a.e[sl] = T(0);
 #pragma unroll
                 for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
             }
-            continue;
-        }
-        T r[N - 1][J];
-        T d[J];
-        if constexpr (GA) {
-            int32_t ii[N - 1];
-            ii[0] = i0;
-#pragma unroll
-            for (int m = 1; m < N - 1; ++m) ii[m] = a.oidx[m][sl];
-            delta_gather<N, J, T>(Gt, Gnz, a.fac, a.omask, ii, r, d);
-            if constexpr (OP == OP_RESID) {
-                // the slot copy of the mode N-2 row must hold the values even
-                // when delta vanished without loading them
-                load_row<J, T>(a.fac[N - 2] + (int64_t)ii[N - 2] * J, r[N - 2]);
-            }
         } else {
-            load_row<J, T>(a.fac[0] + (int64_t)i0 * J, r[0]);
-#pragma unroll
-            for (int m = 1; m < N - 1; ++m) load_row<J, T>(a.fac[m] + (int64_t)a.oidx[m][sl] * J, r[m]);
-            delta_vec<N, J, T>(Gp, r, d);
-        }
-        const T x = a.xval[sl];
-        if constexpr (OP == OP_SWEEP) {
-#pragma unroll
-            for (int t = 0; t < J; ++t) {
-                s[t] = vfma(x, d[t], s[t]);
-#pragma unroll
-                for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[t], d[v], s[J + sym<J>(t, v)]);
-            }
-        } else {
-            T b = own[0] * d[0];
-#pragma unroll
-            for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
-            if constexpr (OP == OP_KEYS) {
-                const T ev = x - b;
-#pragma unroll
-                for (int t = 0; t < J; ++t) {
-                    s[t] = vfma(ev, d[t], s[t]);
-                    s[J + t] = vfma(d[t], d[t], s[J + t]);
+            T r[N - 1][J];
+            T d[J];
+            if constexpr (GA) {
+                uint32_t mk[N - 1];
+                load_marks(ci, mk);
+                delta_gather<N, J, T>(Gt, Gnz, a.fac, ci, mk, r, d);
+                if constexpr (OP == OP_RESID) {
+                    // the slot copy of the mode N-2 row must hold the values
+                    // even when delta vanished without loading them
+                    load_row<J, T>(a.fac[N - 2] + (int64_t)ci[N - 2] * J, r[N - 2]);
                 }
             } else {
-                a.e[sl] = x - b;
 #pragma unroll
-                for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
+                for (int m = 0; m < N - 1; ++m) load_row<J, T>(a.fac[m] + (int64_t)ci[m] * J, r[m]);
+                delta_vec<N, J, T>(Gp, r, d);
+            }
+            const T x = cx;
+            if constexpr (OP == OP_SWEEP) {
+#pragma unroll
+                for (int t = 0; t < J; ++t) {
+                    s[t] = vfma(x, d[t], s[t]);
+#pragma unroll
+                    for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(d[t], d[v], s[J + sym<J>(t, v)]);
+                }
+            } else {
+                T b = own[0] * d[0];
+#pragma unroll
+                for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);
+                if constexpr (OP == OP_KEYS) {
+                    const T ev = x - b;
+#pragma unroll
+                    for (int t = 0; t < J; ++t) {
+                        s[t] = vfma(ev, d[t], s[t]);
+                        s[J + t] = vfma(d[t], d[t], s[J + t]);
+                    }
+                } else {
+                    a.e[sl] = x - b;
+#pragma unroll
+                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
+                }
             }
         }
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) {
+            ci[m] = ni[m];
+        }
+        cx = nx;
     }
     if constexpr (OP == OP_RESID) {
         return;
@@ -482,10 +506,12 @@ __global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, c
 }
 
 // Kernel choice for the contraction of mode `mode` (the factors of the other
-// modes enter).  AUTO compares the expected number of surviving terms per
-// entry, E = prod_{k != mode} J d_k (d_k = unmarked fraction of A^(k)), each
-// costing J LDS reads and fused multiply-adds, with the dense contraction's
-// sum_{m=2..N} J^m operations (a quarter of that on the matrix-core form).
+// modes enter).  AUTO compares costs in fused multiply-adds per entry: the
+// dense contraction's sum_{m=2..N} J^m (a quarter of that on the matrix-core
+// form) against the gather form's fixed cost G0 (its dependent loads of
+// marking words and rows; 550, measured as half the dense FP64 cost at order
+// 3, rank 10) plus 10 J per expected surviving term, E = prod_{k != mode}
+// J d_k (d_k = unmarked fraction of A^(k)).
 static bool use_gather(const vest_ctx *c, int mode, bool dense_on_mfma)
 {
     if (c->kernel_policy == VEST_KERNEL_DENSE) return false;
@@ -499,7 +525,7 @@ static bool use_gather(const vest_ctx *c, int mode, bool dense_on_mfma)
     }
     for (int m = 2; m <= N; ++m) D += (p *= J);
     if (dense_on_mfma) D *= 0.25;
-    return 3.0 * E * J < D;
+    return 550.0 + 10.0 * J * E < D;
 }
 
 template <int N, int J, typename T>
