@@ -145,6 +145,17 @@ int vest_prune(vest_ctx *ctx, int64_t core_k, const int64_t *factor_k);
  * out is a host array of 5 doubles.  Synchronises the stream. */
 int vest_loss(vest_ctx *ctx, double *out);
 
+/* Drop from the per-mode layouts the observed entries that can no longer
+ * contribute: those with a fully marked factor row in some mode (Sec. 3.3;
+ * marks never clear).  Their reconstruction, every delta term, core weight
+ * and key contribution are zero for good, so every later call returns the
+ * same results with or without them (up to rounding order); their residual
+ * stays X_alpha and sum X^2 over them is kept for vest_loss.  Rebuilds the
+ * layouts inside the workspace from the kept entries (no caller array is
+ * needed) and synchronises the stream.  *live (may be NULL) receives the
+ * number of entries kept; nothing changes when all are live or none is. */
+int vest_compact(vest_ctx *ctx, int64_t *live);
+
 /* Contraction kernel of the factor sweeps, factor keys and residual passes
  * (Eq. 11):
  *   VEST_KERNEL_AUTO    per call, from the marked fractions of the factors

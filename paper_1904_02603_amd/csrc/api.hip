@@ -111,10 +111,10 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     for (int n = 0; n < N; ++n) {
         ModeLayout &L = c->lay[n];
         const int64_t sb = p.slot_bound[n];
-        L.nslots = sb;
-        L.nwaves = (int32_t)p.wave_bound[n];
-        L.nlong = (int32_t)p.long_bound[n];
-        L.nchunks = (int32_t)p.chunk_bound;
+        L.cap_slots = L.nslots = sb;
+        L.cap_waves = L.nwaves = (int32_t)p.wave_bound[n];
+        L.cap_long = L.nlong = (int32_t)p.long_bound[n];
+        L.cap_chunks = L.nchunks = (int32_t)p.chunk_bound;
         L.waves = (WaveInfo *)take(p.wave_bound[n] * sizeof(WaveInfo));
         L.row_order = (int32_t *)take(c->d.dims[n] * 4);
         for (int m = 0; m < N - 1; ++m) L.oidx[m] = (int32_t *)take(sb * 4);
@@ -122,8 +122,18 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
         L.perm = (int32_t *)take(sb * 4);
         L.longrows = (LongRow *)take(p.long_bound[n] * sizeof(LongRow));
     }
-    c->e = take(p.slot_bound[N - 1] * ts);
-    c->ms = take((p.slot_bound[N - 1] + 63) / 64 * 64 * J * ts);
+    // e and ms are contiguous; together they also stage a compaction
+    // (vest_compact): mode-0 slot flags and positions, wave partials, the
+    // live entries' indices and values
+    const size_t e_bytes = (size_t)p.slot_bound[N - 1] * ts;
+    size_t ms_bytes = (size_t)(p.slot_bound[N - 1] + 63) / 64 * 64 * J * ts;
+    const size_t stage_need = 2 * ((size_t)p.slot_bound[0] * 4 + 256) + ((size_t)p.wave_bound[0] * 8 + 264) +
+                              ((size_t)c->d.nnz * N * 4 + 256) + ((size_t)c->d.nnz * 8 + 256);
+    if (e_bytes + 256 + ms_bytes < stage_need) ms_bytes = stage_need - e_bytes;
+    c->e = take(e_bytes);
+    c->ms = take(ms_bytes);
+    c->stage = c->e;
+    c->stage_bytes = (size_t)((char *)c->ms - (char *)c->e) + ms_bytes;
     c->hdiag = (double *)take(c->G * 8);
     for (int n = 0; n < N; ++n) c->Gp[n] = take(c->G * ts);
     for (int n = 0; n < N; ++n)
@@ -307,6 +317,8 @@ int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const dou
     char *scratch = nullptr;
     if (!carve(c, p, b, &scratch)) { delete c; set_error("workspace carve failed"); return VEST_ENOSPC; }
 
+    c->scratch = scratch;
+    c->scratch_bytes = p.scratch_bytes;
     int bad = 0;
     he = build_layouts(c, idx, val, scratch, p.scratch_bytes, &bad);
     if (he != hipSuccess) { int r = device_error(nullptr, he, "layout"); delete c; return r; }
@@ -430,11 +442,36 @@ int vest_loss(vest_ctx *c, double *out)
     double h[2];
     CALL_HIP(c, hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, c->stream), "loss copy");
     CALL_HIP(c, hipStreamSynchronize(c->stream), "loss sync");
-    out[0] = h[0];
+    out[0] = h[0] + c->sse_dead;
     out[1] = c->xnorm2;
     out[2] = c->d.lambda * h[1];
     out[3] = out[0] + out[2];
     out[4] = c->xnorm2 > 0 ? std::sqrt(out[0] / c->xnorm2) : 0.0;
+    return VEST_OK;
+}
+
+int vest_compact(vest_ctx *c, int64_t *live_out)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    int32_t *idx = nullptr;
+    double *val = nullptr;
+    int64_t nlive = 0;
+    double dsq = 0.0;
+    CALL_HIP(c, launch_compact(c, &idx, &val, &nlive, &dsq), "compaction");
+    if (live_out) *live_out = nlive;
+    if (nlive == c->d.nnz || nlive == 0) return VEST_OK;  // nothing to drop / keep the layout
+    c->d.nnz = nlive;
+    int bad = 0;
+    // the build scratch carved for the original entry count bounds the one
+    // the smaller build needs
+    hipError_t he = build_layouts(c, idx, val, c->scratch, c->scratch_bytes, &bad);
+    if (he != hipSuccess) return device_error(c, he, "compaction layout");
+    if (bad) { set_error("compaction produced an invalid entry set (%d)", bad); c->dead = true; return VEST_EDEVICE; }
+    c->sse_dead += dsq;
+    c->e_valid = false;
+    c->ms_valid = false;
+    c->hdiag_valid = false;
     return VEST_OK;
 }
 

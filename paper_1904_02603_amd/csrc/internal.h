@@ -60,6 +60,10 @@ struct LongRow {
 };
 
 struct ModeLayout {
+    // capacities of the workspace regions (fixed at carve time)
+    int64_t cap_slots = 0;
+    int32_t cap_waves = 0, cap_long = 0, cap_chunks = 0;
+    // current layout
     int64_t nslots = 0;
     int64_t npad = 0;
     int32_t nwaves = 0;
@@ -153,6 +157,11 @@ struct vest_ctx {
 
     // bookkeeping
     double xnorm2 = 0.0;
+    double sse_dead = 0.0;            // sum X^2 of the entries dropped by vest_compact
+    void *stage = nullptr;            // compaction staging (spans the e and ms regions)
+    size_t stage_bytes = 0;
+    char *scratch = nullptr;          // layout-build scratch
+    size_t scratch_bytes = 0;
     int64_t marked_core = 0;
     int64_t marked_fac[VEST_MAX_ORDER] = {};
     uint64_t core_version = 1;
@@ -175,6 +184,9 @@ bool shape_supported(int N, int J);
 
 hipError_t launch_rowgroup(vest_ctx *c, int mode, int op);       // OP_SWEEP / OP_KEYS / OP_RESID
 hipError_t launch_core_sweep(vest_ctx *c);
+// Live entries of the mode-0 layout re-assembled into (idx, val) in `stage`;
+// *live and *dead_sq (sum X^2 of the dropped ones) on return (synchronises).
+hipError_t launch_compact(vest_ctx *c, int32_t **idx, double **val, int64_t *live, double *dead_sq);
 hipError_t launch_core_keys(vest_ctx *c, double *core_key);
 hipError_t launch_permute_core(vest_ctx *c, int mode);
 hipError_t launch_cast_factor(vest_ctx *c, int mode);

@@ -278,9 +278,8 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
 
         HostPlan hp;
         plan_mode(cnt, hp);
-        if (hp.nslots > c->lay[n].nslots || (int64_t)hp.waves.size() > L.nwaves ||
-            (int64_t)hp.longrows.size() > L.nlong || hp.nchunks > L.nchunks) {
-            // capacities were stored in the layout by the carve step
+        if (hp.nslots > L.cap_slots || (int64_t)hp.waves.size() > L.cap_waves ||
+            (int64_t)hp.longrows.size() > L.cap_long || hp.nchunks > L.cap_chunks) {
             return hipErrorOutOfMemory;
         }
         L.nslots = hp.nslots;
@@ -318,6 +317,138 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
     }
 
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ compaction
+// An entry is dead once some mode's row of it is fully marked: its
+// reconstruction B(alpha) and every delta, core weight and key term of it
+// are zero for good (marks never clear).  One wave per wave of the mode-0
+// layout marks the live slots and sums X^2 of the dead ones.
+struct MaskArg {
+    const uint32_t *p[VEST_MAX_ORDER];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_live(const WaveInfo *__restrict__ waves, const int32_t *__restrict__ row_order,
+                                             OidxArg oidx, const T *__restrict__ xval, MaskArg mk, int N,
+                                             uint32_t full, uint32_t *__restrict__ flags, double *__restrict__ dsq)
+{
+    __shared__ double sh[64];
+    const WaveInfo wi = waves[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int grp = lane >> wi.glog;
+    const int32_t row = grp < wi.nrows ? row_order[wi.first + grp] : 0;
+    double acc = 0.0;
+    for (int k = 0; k < wi.K; ++k) {
+        const int64_t s = wi.base + (int64_t)k * 64 + lane;
+        uint32_t alive = 0;
+        if (oidx.p[0][s] >= 0) {
+            bool ok = (~mk.p[0][row] & full) != 0u;
+            for (int m = 1; m < N; ++m) ok = ok && (~mk.p[m][oidx.p[m - 1][s]] & full) != 0u;
+            alive = ok ? 1u : 0u;
+            if (!ok) {
+                const double x = (double)xval[s];
+                acc += x * x;
+            }
+        }
+        flags[s] = alive;
+    }
+    sh[lane] = acc;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (lane < w) sh[lane] += sh[lane + w];
+        __syncthreads();
+    }
+    if (lane == 0) dsq[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_gather_live(const WaveInfo *__restrict__ waves,
+                                                    const int32_t *__restrict__ row_order, OidxArg oidx,
+                                                    const T *__restrict__ xval, int N,
+                                                    const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
+                                                    int32_t *__restrict__ idx, double *__restrict__ val)
+{
+    const WaveInfo wi = waves[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int grp = lane >> wi.glog;
+    const int32_t row = grp < wi.nrows ? row_order[wi.first + grp] : 0;
+    for (int k = 0; k < wi.K; ++k) {
+        const int64_t s = wi.base + (int64_t)k * 64 + lane;
+        if (!flags[s]) continue;
+        const int64_t q = pos[s];
+        idx[q * N] = row;
+        for (int m = 1; m < N; ++m) idx[q * N + m] = oidx.p[m - 1][s];
+        val[q] = (double)xval[s];
+    }
+}
+
+__global__ void k_sum_fixed(const double *__restrict__ part, int64_t n, double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+hipError_t launch_compact(vest_ctx *c, int32_t **idx_out, double **val_out, int64_t *live, double *dead_sq)
+{
+    const int N = c->N;
+    const ModeLayout &L = c->lay[0];
+    hipStream_t st = c->stream;
+    const int64_t ns = L.nslots;
+    Bump b{(char *)c->stage, 0, c->stage_bytes};
+    auto *flags = (uint32_t *)b.take(ns * 4);
+    auto *pos = (uint32_t *)b.take(ns * 4);
+    auto *dsq = (double *)b.take((size_t)L.nwaves * 8 + 8);
+    auto *idx = (int32_t *)b.take((size_t)c->d.nnz * N * 4);
+    auto *val = (double *)b.take((size_t)c->d.nnz * 8);
+    if (!flags || !pos || !dsq || !idx || !val) return hipErrorOutOfMemory;
+    OidxArg oa{};
+    for (int m = 0; m < N - 1; ++m) oa.p[m] = L.oidx[m];
+    MaskArg mk{};
+    for (int n = 0; n < N; ++n) mk.p[n] = c->fmask[n];
+    const uint32_t full = c->J == 32 ? 0xffffffffu : (1u << c->J) - 1u;
+    if (L.nwaves > 0) {
+        if (c->f32)
+            hipLaunchKernelGGL(k_live<float>, dim3(L.nwaves), dim3(64), 0, st, L.waves, L.row_order, oa,
+                               reinterpret_cast<const float *>(L.xval), mk, N, full, flags, dsq);
+        else
+            hipLaunchKernelGGL(k_live<double>, dim3(L.nwaves), dim3(64), 0, st, L.waves, L.row_order, oa,
+                               reinterpret_cast<const double *>(L.xval), mk, N, full, flags, dsq);
+    }
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, dsq, (int64_t)L.nwaves, dsq + L.nwaves);
+    size_t tb = 0;
+    CHECK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flags, pos, (int)ns, st));
+    if (tb > c->sort_tmp_bytes) return hipErrorOutOfMemory;
+    tb = c->sort_tmp_bytes;
+    CHECK_HIP(hipcub::DeviceScan::ExclusiveSum(c->sort_tmp, tb, flags, pos, (int)ns, st));
+    if (L.nwaves > 0) {
+        if (c->f32)
+            hipLaunchKernelGGL(k_gather_live<float>, dim3(L.nwaves), dim3(64), 0, st, L.waves, L.row_order, oa,
+                               reinterpret_cast<const float *>(L.xval), N, flags, pos, idx, val);
+        else
+            hipLaunchKernelGGL(k_gather_live<double>, dim3(L.nwaves), dim3(64), 0, st, L.waves, L.row_order, oa,
+                               reinterpret_cast<const double *>(L.xval), N, flags, pos, idx, val);
+    }
+    CHECK_HIP(hipGetLastError());
+    uint32_t tail[2] = {0, 0};
+    double d = 0.0;
+    CHECK_HIP(hipMemcpyAsync(&tail[0], pos + ns - 1, 4, hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipMemcpyAsync(&tail[1], flags + ns - 1, 4, hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipMemcpyAsync(&d, dsq + L.nwaves, 8, hipMemcpyDeviceToHost, st));
+    CHECK_HIP(hipStreamSynchronize(st));
+    *live = (int64_t)tail[0] + tail[1];
+    *dead_sq = d;
+    *idx_out = idx;
+    *val_out = val;
+    return hipSuccess;
 }
 
 }  // namespace vest

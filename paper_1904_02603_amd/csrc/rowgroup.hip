@@ -212,17 +212,19 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
-    // Software pipeline: the indices and value of step k + 1 are loaded at
-    // the top of step k and, in the gather form, the marking words of step
-    // k + 1 before the row statistics of step k, so a step waits for one
-    // memory latency (its factor rows) instead of a chain of two or three.
-    // The prefetch of the last step re-reads that step (in range).
+    // Software pipeline: the indices and value of step k + 1 (gather form:
+    // k + 2) are loaded at the top of step k, and in the gather form the
+    // marking words of step k + 1 as well, so a step waits for one memory
+    // latency (its factor rows) instead of a chain of two or three.
+    // Prefetches past the last step re-read that step (in range).
     constexpr uint32_t full = J == 32 ? 0xffffffffu : (1u << J) - 1u;
+    constexpr int AHEAD = GA ? 2 : 1;
     const int K = wi.K;
-    int32_t ci[N - 1];
-    T cx = T(0);
+    int32_t ci[N - 1], pi[N - 1];
+    uint32_t cm[N - 1];
+    T cx = T(0), px = T(0);
     auto load_step = [&](int k, int32_t (&ii)[N - 1], T &x) {
-        const int64_t sl = wi.base + (int64_t)k * kWave + lane;
+        const int64_t sl = wi.base + (int64_t)(k < K ? k : K - 1) * kWave + lane;
 #pragma unroll
         for (int m = 0; m < N - 1; ++m) ii[m] = a.oidx[m][sl];
         x = a.xval[sl];
@@ -231,13 +233,21 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
         for (int m = 0; m < N - 1; ++m) mm[m] = ii[0] >= 0 ? (~a.omask[m][ii[m]] & full) : 0u;
     };
-    if (K > 0) load_step(0, ci, cx);
+    if (K > 0) {
+        load_step(0, ci, cx);
+        if constexpr (GA) {
+            load_marks(ci, cm);
+            load_step(1, pi, px);
+        }
+    }
 #pragma unroll 1
     for (int k = 0; k < K; ++k) {
         const int64_t sl = wi.base + (int64_t)k * kWave + lane;
         int32_t ni[N - 1];
+        uint32_t nm[N - 1];
         T nx;
-        load_step(k + 1 < K ? k + 1 : k, ni, nx);
+        load_step(k + AHEAD, ni, nx);
+        if constexpr (GA) load_marks(pi, nm);
         if (ci[0] < 0) {
             if constexpr (OP == OP_RESID) {
                 a.e[sl] = T(0);
@@ -248,9 +258,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
             T r[N - 1][J];
             T d[J];
             if constexpr (GA) {
-                uint32_t mk[N - 1];
-                load_marks(ci, mk);
-                delta_gather<N, J, T>(Gt, Gnz, a.fac, ci, mk, r, d);
+                delta_gather<N, J, T>(Gt, Gnz, a.fac, ci, cm, r, d);
                 if constexpr (OP == OP_RESID) {
                     // the slot copy of the mode N-2 row must hold the values
                     // even when delta vanished without loading them
@@ -287,11 +295,20 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
                 }
             }
         }
+        if constexpr (GA) {
 #pragma unroll
-        for (int m = 0; m < N - 1; ++m) {
-            ci[m] = ni[m];
+            for (int m = 0; m < N - 1; ++m) {
+                ci[m] = pi[m];
+                pi[m] = ni[m];
+                cm[m] = nm[m];
+            }
+            cx = px;
+            px = nx;
+        } else {
+#pragma unroll
+            for (int m = 0; m < N - 1; ++m) ci[m] = ni[m];
+            cx = nx;
         }
-        cx = nx;
     }
     if constexpr (OP == OP_RESID) {
         return;

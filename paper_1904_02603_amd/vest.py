@@ -21,8 +21,8 @@ FP64, FP32, BF16 = 0, 1, 2
 KERNEL_AUTO, KERNEL_DENSE, KERNEL_GATHER = 0, 1, 2
 
 EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
-           "vest_responsibility", "vest_prune", "vest_loss", "vest_set_kernel", "vest_layout_stats",
-           "vest_destroy", "vest_strerror", "vest_last_error",
+           "vest_responsibility", "vest_prune", "vest_loss", "vest_compact", "vest_set_kernel",
+           "vest_layout_stats", "vest_destroy", "vest_strerror", "vest_last_error",
            "vest_server_create", "vest_server_submit", "vest_server_progress", "vest_server_status",
            "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -68,6 +68,7 @@ def load_library(path=LIB_PATH):
     lib.vest_prune.argtypes = [vp, i64, vp]
     lib.vest_loss.argtypes = [vp, vp]
     lib.vest_set_kernel.argtypes = [vp, i32]
+    lib.vest_compact.argtypes = [vp, C.POINTER(i64)]
     lib.vest_layout_stats.argtypes = [vp, i32, vp]
     lib.vest_destroy.argtypes = [vp]
     lib.vest_strerror.argtypes = [C.c_int]
@@ -85,8 +86,8 @@ def load_library(path=LIB_PATH):
                  "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]:
         getattr(lib, name).restype = C.c_int
     for name in ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
-                 "vest_responsibility", "vest_prune", "vest_loss", "vest_set_kernel", "vest_layout_stats",
-                 "vest_destroy"]:
+                 "vest_responsibility", "vest_prune", "vest_loss", "vest_compact", "vest_set_kernel",
+                 "vest_layout_stats", "vest_destroy"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -214,6 +215,12 @@ class VestContext:
         for n in range(self.N):
             self.sweep_factor(n)
         self.sweep_core()
+
+    def compact(self):
+        """Drop entries with a fully marked row in some mode; returns the kept count."""
+        live = C.c_int64(0)
+        _check(self.lib.vest_compact(self.ctx, C.byref(live)), "vest_compact")
+        return live.value
 
     def set_kernel(self, kernel):
         """Contraction kernel policy: KERNEL_AUTO, KERNEL_DENSE or KERNEL_GATHER."""

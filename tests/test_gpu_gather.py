@@ -80,3 +80,53 @@ def test_bad_kernel_policy_is_rejected():
         g.set_kernel(7)
     assert ei.value.code == v.EINVAL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[2], SHAPES[4], SHAPES[6]], ids=[IDS[1], IDS[2], IDS[4], IDS[6]])
+def test_compaction_keeps_every_result(shape):
+    # entries with a fully marked row are dropped; the loss right after, and
+    # the following iteration, keys and prune, equal the oracle's on the full set
+    dims, ranks, nnz, zipf = shape
+    p = make(dims, ranks, nnz, 48, zipf)
+    fmask, cmask = planted_masks(p, 0.85, 49)
+    g, o = pair(p, REG_LF, 0.05, fmask=fmask, cmask=cmask)
+    before = g.loss()
+    live = g.compact()
+    after = g.loss()
+    say("kept", live, "of", nnz)
+    assert 0 < live < nnz
+    assert g.layout_stats(0)["nnz"] == live
+    assert abs(after["loss"] - before["loss"]) <= 1e-12 * before["loss"]
+    ol = o.loss()
+    assert abs(after["sse"] - ol["sse"]) <= 1e-10 * ol["sse"]
+    for it in range(2):
+        g.iteration()
+        o.iteration()
+        assert_state(g, o, what="compacted iteration %d" % it)
+    gck, gfk = g.responsibility()
+    ock, ofk = o.responsibility()
+    keys_close(gck, ock, "core keys")
+    for n in range(len(dims)):
+        keys_close(gfk[n], ofk[n], "factor keys %d" % n)
+    kc = int(0.05 * p["core"].size)
+    kf = [int(0.05 * f.size) for f in p["factors"]]
+    g.prune(kc, kf)
+    o.prune(ock, ofk, kc, kf)
+    live2 = g.compact()
+    assert live2 <= live
+    g.iteration()
+    o.iteration()
+    assert_state(g, o, what="after second compaction")
+    gl, ol = g.loss(), o.loss()
+    assert abs(gl["re"] - ol["re"]) <= 1e-10 * ol["re"]
+
+
+def test_compaction_in_the_fp32_form():
+    p = make((200, 150, 100), (10, 10, 10), 20_000, 50)
+    fmask, cmask = planted_masks(p, 0.9, 51)
+    g, o = pair(p, REG_LF, 0.05, precision=V().FP32, fmask=fmask, cmask=cmask)
+    g.compact()
+    g.iteration()
+    o.iteration()
+    gl, ol = g.loss(), o.loss()
+    assert abs(gl["loss"] - ol["loss"]) / ol["loss"] <= 1e-6
