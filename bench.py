@@ -181,6 +181,31 @@ def sparse_phase(p, frac, steps, precision):
     gbs = alg / (out["gather_ms_per_sweep"] / 1e3) / 1e9
     out["gather_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s",
                               "frac": gbs / HBM_PEAK}
+    # entries with a fully marked row dropped from the layouts (vest_compact)
+    t0 = time.perf_counter()
+    live = ctx.compact()
+    out["compaction_s"] = time.perf_counter() - t0
+    out["live_entries"] = live
+    ctx.set_kernel(vest.KERNEL_AUTO)
+    for n in range(N):
+        ctx.sweep_factor(n)
+    ev = []
+    for _ in range(steps):
+        for n in range(N):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.sweep_factor(n)
+            b.record(stream)
+            ev.append((a, b))
+    torch.cuda.synchronize()
+    ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+    out["compacted_ms_per_sweep"] = ms
+    out["compacted_entry_updates_per_s"] = nnz / (ms / 1e3)
+    alg_live = live * ((N - 1) * 4 + vb) + sum(f.shape[0] * f.shape[1] * 8 for f in p["factors"]) * (N + 1) / N
+    gl = alg_live / (ms / 1e3) / 1e9
+    out["compacted_roofline"] = {"bound": "hbm", "achieved": gl, "peak": HBM_PEAK, "unit": "GB/s",
+                                 "frac": gl / HBM_PEAK, "algorithmic_bytes": alg_live}
     ctx.close()
     return out
 
@@ -379,8 +404,9 @@ def main():
             log("pruned-phase sweeps (%s, %.0f %% marked) ..." % (name, 100 * args.sparse_frac))
             sparse[name] = sparse_phase(p, args.sparse_frac, args.steps,
                                         {"fp64": vest.FP64, "fp32": vest.FP32, "bf16": vest.BF16}[name])
-            log("  dense %.3f ms, gather %.3f ms per sweep" % (sparse[name]["dense_ms_per_sweep"],
-                                                            sparse[name]["gather_ms_per_sweep"]))
+            log("  dense %.3f ms, gather %.3f ms per sweep; compacted to %d entries in %.2f s: %.3f ms" % (
+                sparse[name]["dense_ms_per_sweep"], sparse[name]["gather_ms_per_sweep"],
+                sparse[name]["live_entries"], sparse[name]["compaction_s"], sparse[name]["compacted_ms_per_sweep"]))
     serving = None
     if args.serve_jobs > 0:
         log("serving stream (%d jobs) ..." % args.serve_jobs)

@@ -63,10 +63,16 @@ def sparsity(ctx):
     return zeros / total
 
 
-def run(ctx, iterations, schedule=None, tol=None, log=None):
-    """Alg. 2 on a VestContext: factor sweeps, core sweep, RE, maybe prune."""
+def run(ctx, iterations, schedule=None, tol=None, log=None, compact_every=5):
+    """Alg. 2 on a VestContext: factor sweeps, core sweep, RE, maybe prune.
+
+    Entries with a fully marked row are dropped from the layouts (vest_compact)
+    every `compact_every` prune steps and once pruning has stopped (0 = never);
+    results do not change, later passes touch fewer entries.
+    """
     schedule = schedule or PruneSchedule(mode="off")
     re_hist = []
+    prunes, compacted_at = 0, 0
     for t in range(1, iterations + 1):
         ctx.iteration()
         L = ctx.loss()
@@ -80,6 +86,13 @@ def run(ctx, iterations, schedule=None, tol=None, log=None):
             fk = [schedule.count(t, f.numel(), m) for f, m in zip(ctx.factors, fmarked)]
             ctx.prune(ck, fk)
             pruned = True
+            prunes += 1
+            if compact_every and prunes - compacted_at >= compact_every:
+                ctx.compact()
+                compacted_at = prunes
+        elif compact_every and prunes > compacted_at:
+            ctx.compact()
+            compacted_at = prunes
         if log is not None:
             log({"iter": t, "re": L["re"], "loss": L["loss"], "sparsity": sp, "pruned": pruned})
         if tol is not None and len(re_hist) > 1 and abs(re_hist[-1] - re_hist[-2]) < tol and not pruned:

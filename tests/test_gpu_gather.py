@@ -130,3 +130,23 @@ def test_compaction_in_the_fp32_form():
     o.iteration()
     gl, ol = g.loss(), o.loss()
     assert abs(gl["loss"] - ol["loss"]) / ol["loss"] <= 1e-6
+
+
+def test_schedule_loop_with_and_without_compaction_agree():
+    from paper_1904_02603_amd.schedule import PruneSchedule, run
+    v = V()
+    p = make((200, 150, 100), (5, 5, 5), 20_000, 52)
+    hist = []
+    ctxs = []
+    for every in (0, 2):
+        g = v.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=REG_LF, lam=0.05)
+        sched = PruneSchedule(mode="manual", target=0.9, init_pr=0.1, max_pr=0.3)
+        hist.append(run(g, 10, sched, compact_every=every))
+        ctxs.append(g)
+    say("RE", hist[0][-1], hist[1][-1], "kept", ctxs[1].layout_stats(0)["nnz"])
+    assert ctxs[1].layout_stats(0)["nnz"] < p["idx"].shape[0]
+    for a, b in zip(*hist):
+        assert abs(a - b) <= 1e-10 * abs(a)
+    for n in range(3):
+        a, b = ctxs[0].factors[n].cpu().numpy(), ctxs[1].factors[n].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
