@@ -37,36 +37,88 @@ __host__ __device__ constexpr int sym(int t, int u)
 __device__ __forceinline__ double vfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float vfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// Contraction of one core slice with the rows of the other modes
-// (Eq. 11): for the slice G[j_n, ...] of the mode-n-permuted core,
-//   sum over (o_0 .. o_{NO-1}) of G[o_0, .., o_{NO-1}] * prod_m r[m][o_m],
-// innermost mode first.  All offsets are compile-time constants; G is a
-// wave-uniform pointer, so the core operands come through scalar loads.
-template <int NO, int J, int D, typename T>
-__device__ __forceinline__ T contract(const T *__restrict__ G, const T (&r)[NO][J])
+// Core operands are wave-uniform and read with scalar loads.  A scalar
+// load's immediate offset reaches 4 KB, so the core is addressed through one
+// base pointer per 4 KB window; each base is made opaque to the compiler,
+// which would otherwise fold it back into one large offset and then
+// materialise a separate 64-bit base for every load beyond the window (about
+// forty extra scalar-register pairs, spilled, leaving no room to load the
+// next operands while the current ones are consumed).  The pointers are in
+// the constant address space so the loads stay scalar.
+template <typename T>
+struct CoreBases {
+    static constexpr int W = 4096 / (int)sizeof(T);
+    typedef const __attribute__((address_space(4))) T *CPtr;
+    CPtr b[64];
+};
+
+template <int N, int J, typename T>
+__device__ __forceinline__ CoreBases<T> core_bases(const T *__restrict__ Gp)
 {
-    if constexpr (D == NO - 1) {
-        T acc = G[0] * r[D][0];
+    constexpr int W = CoreBases<T>::W;
+    static_assert((ipow(J, N) + W - 1) / W <= 64, "core windows");
+    CoreBases<T> G;
 #pragma unroll
-        for (int o = 1; o < J; ++o) acc = vfma(G[o], r[D][o], acc);
+    for (int k = 0; k < (ipow(J, N) + W - 1) / W; ++k) {
+        uint64_t q = reinterpret_cast<uint64_t>(Gp + k * W);
+        asm("" : "+s"(q));
+        G.b[k] = (typename CoreBases<T>::CPtr)q;
+    }
+    return G;
+}
+
+template <int F, typename T>
+__device__ __forceinline__ T core_at(const CoreBases<T> &G)
+{
+    constexpr int W = CoreBases<T>::W;
+    return G.b[F / W][F % W];
+}
+
+// Contraction of one core slice with the rows of the other modes
+// (Eq. 11): for the slice starting at flat offset F of the
+// mode-n-permuted core, the sum over (o_D .. o_{NO-1}) of
+// G[F + ...] * prod_m r[m][o_m], innermost mode first, terms added in
+// ascending o.  All offsets are compile-time constants.
+template <int NO, int J, int D, int F, typename T>
+__device__ __forceinline__ T contract(const CoreBases<T> &G, const T (&r)[NO][J]);
+
+template <int NO, int J, int D, int F, int O, typename T>
+__device__ __forceinline__ T contract_rest(const CoreBases<T> &G, const T (&r)[NO][J], T acc)
+{
+    if constexpr (O == J) {
         return acc;
     } else {
-        constexpr int stride = ipow(J, NO - 1 - D);
-        T acc = contract<NO, J, D + 1, T>(G, r) * r[D][0];
-#pragma unroll
-        for (int o = 1; o < J; ++o) acc = vfma(contract<NO, J, D + 1, T>(G + o * stride, r), r[D][o], acc);
-        return acc;
+        T v;
+        if constexpr (D == NO - 1) v = core_at<F + O>(G);
+        else v = contract<NO, J, D + 1, F + O * ipow(J, NO - 1 - D), T>(G, r);
+        return contract_rest<NO, J, D, F, O + 1, T>(G, r, vfma(v, r[D][O], acc));
+    }
+}
+
+template <int NO, int J, int D, int F, typename T>
+__device__ __forceinline__ T contract(const CoreBases<T> &G, const T (&r)[NO][J])
+{
+    T v0;
+    if constexpr (D == NO - 1) v0 = core_at<F>(G);
+    else v0 = contract<NO, J, D + 1, F, T>(G, r);
+    return contract_rest<NO, J, D, F, 1, T>(G, r, v0 * r[D][0]);
+}
+
+template <int N, int J, int j, typename T>
+__device__ __forceinline__ void delta_from(const CoreBases<T> &G, const T (&r)[N - 1][J], T (&d)[J])
+{
+    if constexpr (j < J) {
+        d[j] = contract<N - 1, J, 0, j * ipow(J, N - 1), T>(G, r);
+        delta_from<N, J, j + 1, T>(G, r, d);
     }
 }
 
 // delta_alpha^{(n)} (Eq. 11) for one entry, given the permuted core Gp
 // ([J_n][others ascending], row-major) and the N-1 other-mode factor rows.
 template <int N, int J, typename T>
-__device__ __forceinline__ void delta_vec(const T *__restrict__ Gp, const T (&r)[N - 1][J], T (&d)[J])
+__device__ __forceinline__ void delta_vec(const CoreBases<T> &G, const T (&r)[N - 1][J], T (&d)[J])
 {
-    constexpr int slice = ipow(J, N - 1);
-#pragma unroll
-    for (int j = 0; j < J; ++j) d[j] = contract<N - 1, J, 0, T>(Gp + j * slice, r);
+    delta_from<N, J, 0, T>(G, r, d);
 }
 
 // Slot-ordered copy of a per-entry factor row, interleaved per wave: the J

@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
     T *Gt = reinterpret_cast<T *>(smem);
     uint32_t *Gnz = reinterpret_cast<uint32_t *>(smem + (size_t)ipow(J, N) * sizeof(T));
     if constexpr (GA) stage_core<N, J, T>(Gp, Gt, Gnz);
+    const CoreBases<T> Gb = core_bases<N, J, T>(Gp);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (wave >= a.nwaves) return;
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
             } else {
 #pragma unroll
                 for (int m = 0; m < N - 1; ++m) load_row<J, T>(a.fac[m] + (int64_t)ci[m] * J, r[m]);
-                delta_vec<N, J, T>(Gp, r, d);
+                delta_vec<N, J, T>(Gb, r, d);
             }
             const T x = cx;
             if constexpr (OP == OP_SWEEP) {
