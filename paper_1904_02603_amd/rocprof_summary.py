@@ -55,9 +55,12 @@ def counters(db):
             print("%-14s %-64s n=%-3d avg/dispatch=%.4g" % (cn, k[:64], len(v), sum(v) / len(v)))
 
 
-def traffic(fetch_db, write_db, kernel):
+def traffic(fetch_db, write_db, kernel, first=None):
     f = _per_dispatch(fetch_db, "FETCH_SIZE")
     w = _per_dispatch(write_db, "WRITE_SIZE")
+    if first is not None:  # only the first `first` dispatches of each kernel
+        f = {k: v[:first] for k, v in f.items()}
+        w = {k: v[:first] for k, v in w.items()}
     ck, cf = _first_copy(fetch_db, "FETCH_SIZE")
     _, cw = _first_copy(write_db, "WRITE_SIZE")
     if ck is None:
@@ -80,4 +83,4 @@ if __name__ == "__main__":
     elif sys.argv[1] == "counters":
         counters(sys.argv[2])
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]) if len(sys.argv) > 5 else None)
