@@ -300,34 +300,55 @@ __global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, i
 // v_mfma_f64_16x16x4 step consumes four rows r: lane l supplies
 // A[l % 16][l / 16] = rb[r0 + l / 16][16 ti + l % 16] and
 // B[l / 16][l % 16] = kp[r0 + l / 16][16 tj + l % 16], and tile element
-// (i, j) ends in lane 16 (i % 4) + j, register i / 4.  Columns past W1 / W2
-// and rows past nrows enter as zeros.
+// (i, j) ends in lane 16 (i % 4) + j, register i / 4.  The kp rows, read by
+// every wave, are staged in LDS 32 at a time; columns past W1 / W2 and rows
+// past nrows enter as zeros.
 template <int W1, int W2>
 __global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__restrict__ rb, int ldrb,
                                                                  const double *__restrict__ kp, int ldkp,
                                                                  int64_t nrows, double *__restrict__ part)
 {
-    constexpr int T2 = (W2 + 15) / 16;
-    static_assert(kGramRows % 4 == 0, "four rows per step");
+    constexpr int T1 = (W1 + 15) / 16, T2 = (W2 + 15) / 16;
+    constexpr int SUB = 32, W2P = 16 * T2, NT = 64 * T1;
+    constexpr int PER = (SUB * W2P + NT - 1) / NT;
+    static_assert(kGramRows % SUB == 0, "sub-blocks of 32 rows");
+    __shared__ double skp[SUB * W2P];
     const int lane = threadIdx.x & (kWave - 1), ti = threadIdx.x / kWave;
     const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
     const int ci = 16 * ti + (lane & 15);
     f64x4 acc[T2];
 #pragma unroll
     for (int tj = 0; tj < T2; ++tj) acc[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k = 0; k < kGramRows; k += 4) {
-        const int64_t r = r0 + k + (lane >> 4);
-        const bool inr = r < nrows;
-        const double av = (inr && ci < W1) ? rb[r * ldrb + ci] : 0.0;
-        double bv[T2];
+    for (int s0 = 0; s0 < kGramRows; s0 += SUB) {
+        double v[PER];
 #pragma unroll
-        for (int tj = 0; tj < T2; ++tj) {
-            const int cj = 16 * tj + (lane & 15);
-            bv[tj] = (inr && cj < W2) ? kp[r * ldkp + cj] : 0.0;
+        for (int i = 0; i < PER; ++i) {
+            const int q = threadIdx.x + i * NT;
+            const int rr = q / W2P, cc = q % W2P;
+            const int64_t r = r0 + s0 + rr;
+            v[i] = (q < SUB * W2P && r < nrows && cc < W2) ? kp[r * ldkp + cc] : 0.0;
         }
+        double av[SUB / 4];
 #pragma unroll
-        for (int tj = 0; tj < T2; ++tj) acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tj], acc[tj], 0, 0, 0);
+        for (int k = 0; k < SUB / 4; ++k) {
+            const int64_t r = r0 + s0 + 4 * k + (lane >> 4);
+            av[k] = (r < nrows && ci < W1) ? rb[r * ldrb + ci] : 0.0;
+        }
+        __syncthreads();  // the previous sub-block's reads of skp are done
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = threadIdx.x + i * NT;
+            if (q < SUB * W2P) skp[q] = v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SUB / 4; ++k) {
+            const int rr = 4 * k + (lane >> 4);
+#pragma unroll
+            for (int tj = 0; tj < T2; ++tj)
+                acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k], skp[rr * W2P + 16 * tj + (lane & 15)], acc[tj], 0,
+                                                              0, 0);
+        }
     }
     double *o = part + (int64_t)blockIdx.x * W1 * W2;
 #pragma unroll
@@ -440,7 +461,29 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
         mbits[c] = __ballot(in && cmask[base + q] != 0);
         if (in) hdiag[base + q] = h;
     }
+    // H(q2, q) for the lane's elements q2 = lane + 64 c: the row parts of the
+    // symmetric index are fixed per lane; the reads for element q + 1 are
+    // issued before the dependent chain of element q.
+    int t2[CPL], u2[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int q2 = lane + c * kWave;
+        t2[c] = q2 < B ? q2 / J : 0;
+        u2[c] = q2 < B ? q2 % J : 0;
+    }
+    auto hcol = [&](int q, double (&hc)[CPL]) {
+        const int t = q / J, u = q % J;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int q2 = lane + c * kWave;
+            hc[c] = (q2 < B && q < B) ? sg[(J + symr(J, t2[c], t)) * GW + J + symr(J, u2[c], u)] : 0.0;
+        }
+    };
+    double hcur[CPL];
+    hcol(0, hcur);
     for (int q = 0; q < B; ++q) {
+        double hnxt[CPL];
+        hcol(q + 1, hnxt);
         const int oc = q / kWave, ol = q % kWave;
         uint64_t mb = mbits[0];
         double g = gv[0], r = rv[0], h = hv[0], iq = iv[0], cc = corr[0];
@@ -454,32 +497,34 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
                 iq = iv[c];
                 cc = corr[c];
             }
-        if ((mb >> ol) & 1ull) continue;
-        g = readlane_d(g, ol);
-        r = readlane_d(r, ol);
-        h = readlane_d(h, ol);
-        iq = readlane_d(iq, ol);
-        cc = readlane_d(cc, ol);
-        // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
-        const double num = r - cc + g * h;
-        double nw;
-        if (reg == VEST_REG_LF) {
-            nw = num * iq;
-        } else {
-            const double gg = -2.0 * num;
-            nw = gg > lambda ? (lambda - gg) * iq : (gg < -lambda ? -(lambda + gg) * iq : 0.0);
-        }
-        const double dq = nw - g;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int q2 = lane + c * kWave;
-            if (c == oc && lane == ol) {
-                gv[c] = nw;
-                dv[c] = dq;
+        if (!((mb >> ol) & 1ull)) {
+            g = readlane_d(g, ol);
+            r = readlane_d(r, ol);
+            h = readlane_d(h, ol);
+            iq = readlane_d(iq, ol);
+            cc = readlane_d(cc, ol);
+            // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
+            const double num = r - cc + g * h;
+            double nw;
+            if (reg == VEST_REG_LF) {
+                nw = num * iq;
+            } else {
+                const double gg = -2.0 * num;
+                nw = gg > lambda ? (lambda - gg) * iq : (gg < -lambda ? -(lambda + gg) * iq : 0.0);
             }
-            const double hq = q2 < B ? H(q2, q) : 0.0;
-            corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hq, dq, corr[c]) : corr[c];
+            const double dq = nw - g;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int q2 = lane + c * kWave;
+                if (c == oc && lane == ol) {
+                    gv[c] = nw;
+                    dv[c] = dq;
+                }
+                corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hcur[c], dq, corr[c]) : corr[c];
+            }
         }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) hcur[c] = hnxt[c];
     }
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
