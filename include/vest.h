@@ -145,6 +145,36 @@ int vest_prune(vest_ctx *ctx, int64_t core_k, const int64_t *factor_k);
  * out is a host array of 5 doubles.  Synchronises the stream. */
 int vest_loss(vest_ctx *ctx, double *out);
 
+/* Final step of Alg. 2: every factor matrix gets unit-length columns,
+ * A^(n) <- A^(n) diag(1 / ||a^(n)_{:t}||), and the core absorbs the norms,
+ * G <- G x_n diag(||a^(n)_{:t}||), modes in order; a zero column stays zero
+ * (its core slice is scaled by 0).  The reconstruction is unchanged. */
+int vest_normalize(vest_ctx *ctx);
+
+/* Number of nonzero values of each factor matrix and of the core (host out,
+ * N + 1 values, modes in order then the core).  Synchronises the stream. */
+int vest_count_nonzeros(vest_ctx *ctx, int64_t *counts);
+
+/* Sparse export of the model (the output of Alg. 2): for each factor matrix
+ * the flat indices i*J_n + j and the values of its nonzero elements in
+ * ascending flat order, and the same for the core (flat order of vest.h).
+ * Device outputs, sized by vest_count_nonzeros; fac_idx / fac_val are host
+ * arrays of N device pointers. */
+int vest_export(vest_ctx *ctx, int64_t *const *fac_idx, double *const *fac_val, int64_t *core_idx,
+                double *core_val);
+
+/* Loss terms of the current model on another set of entries (a held-out
+ * test set; Eq. 4 over that set): idx n*N int32 entry-major, val n FP64,
+ * device arrays.  out (host, 3 doubles): sum (X - B)^2, sum X^2, RE.
+ * VEST_EINVAL for an index out of range.  Synchronises the stream. */
+int vest_test_error(vest_ctx *ctx, const int32_t *idx, const double *val, int64_t n, double *out);
+
+/* Keys of the value-pruning comparator: |value| of every unmarked element,
+ * +infinity for marked ones, written like vest_responsibility's keys and
+ * made the pending keys of the next vest_prune (which then removes the
+ * smallest-magnitude elements). */
+int vest_value_keys(vest_ctx *ctx, double *core_key, double *const *factor_key);
+
 /* Drop from the per-mode layouts the observed entries that can no longer
  * contribute: those with a fully marked factor row in some mode (Sec. 3.3;
  * marks never clear).  Their reconstruction, every delta term, core weight

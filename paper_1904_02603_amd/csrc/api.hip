@@ -475,6 +475,80 @@ int vest_compact(vest_ctx *c, int64_t *live_out)
     return VEST_OK;
 }
 
+int vest_normalize(vest_ctx *c)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    CALL_HIP(c, launch_normalize(c), "normalisation");
+    c->core_version++;
+    for (int n = 0; n < c->N; ++n) c->a32_valid[n] = false;
+    c->e_valid = false;
+    c->ms_valid = false;
+    c->hdiag_valid = false;
+    c->keys_pending = false;
+    if ((rc = ensure_a32(c))) return rc;
+    return refresh_gp(c);
+}
+
+int vest_count_nonzeros(vest_ctx *c, int64_t *counts)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!counts) { set_error("null output"); return VEST_EINVAL; }
+    CALL_HIP(c, launch_count_nonzeros(c, counts), "nonzero count");
+    return VEST_OK;
+}
+
+int vest_export(vest_ctx *c, int64_t *const *fac_idx, double *const *fac_val, int64_t *core_idx, double *core_val)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!fac_idx || !fac_val || !core_idx || !core_val) { set_error("null output"); return VEST_EINVAL; }
+    for (int n = 0; n < c->N; ++n)
+        if (!fac_idx[n] || !fac_val[n]) { set_error("null output of mode %d", n); return VEST_EINVAL; }
+    CALL_HIP(c, launch_export(c, fac_idx, fac_val, core_idx, core_val), "export");
+    return VEST_OK;
+}
+
+int vest_test_error(vest_ctx *c, const int32_t *idx, const double *val, int64_t n, double *out)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!out || (n > 0 && (!idx || !val)) || n < 0) { set_error("bad held-out arguments"); return VEST_EINVAL; }
+    double h[2] = {0.0, 0.0};
+    int32_t fl[16] = {};
+    if (n > 0) {
+        for (int m = 0; m < c->N; ++m)
+            if ((rc = ensure_gp(c, m))) return rc;
+        if ((rc = ensure_a32(c))) return rc;
+        double *dout = c->red + 16 * kLossBlocks;
+        CALL_HIP(c, hipMemsetAsync(c->flags, 0, 64, c->stream), "flags");
+        CALL_HIP(c, launch_heldout(c, idx, val, n, dout), "held-out error");
+        CALL_HIP(c, hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, c->stream), "held-out copy");
+        CALL_HIP(c, hipMemcpyAsync(fl, c->flags, 64, hipMemcpyDeviceToHost, c->stream), "flag copy");
+        CALL_HIP(c, hipStreamSynchronize(c->stream), "held-out sync");
+        if (fl[0]) { set_error("held-out index out of range"); return VEST_EINVAL; }
+    }
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+    return VEST_OK;
+}
+
+int vest_value_keys(vest_ctx *c, double *core_key, double *const *factor_key)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!core_key || !factor_key) { set_error("null key pointer"); return VEST_EINVAL; }
+    for (int n = 0; n < c->N; ++n)
+        if (!factor_key[n]) { set_error("null factor key pointer (mode %d)", n); return VEST_EINVAL; }
+    CALL_HIP(c, launch_value_keys(c, core_key, factor_key), "value keys");
+    for (int n = 0; n < c->N; ++n) c->key_fac[n] = factor_key[n];
+    c->key_core = core_key;
+    c->keys_pending = true;
+    return VEST_OK;
+}
+
 int vest_set_kernel(vest_ctx *c, int32_t kernel)
 {
     if (!c) { set_error("null context"); return VEST_EINVAL; }

@@ -184,6 +184,11 @@ bool shape_supported(int N, int J);
 
 hipError_t launch_rowgroup(vest_ctx *c, int mode, int op);       // OP_SWEEP / OP_KEYS / OP_RESID
 hipError_t launch_core_sweep(vest_ctx *c);
+hipError_t launch_normalize(vest_ctx *c);
+hipError_t launch_count_nonzeros(vest_ctx *c, int64_t *counts);  // synchronises
+hipError_t launch_export(vest_ctx *c, int64_t *const *fi, double *const *fv, int64_t *ci, double *cv);
+hipError_t launch_heldout(vest_ctx *c, const int32_t *idx, const double *val, int64_t n, double *dout);
+hipError_t launch_value_keys(vest_ctx *c, double *core_key, double *const *fkey);
 // Live entries of the mode-0 layout re-assembled into (idx, val) in `stage`;
 // *live and *dead_sq (sum X^2 of the dropped ones) on return (synchronises).
 hipError_t launch_compact(vest_ctx *c, int32_t **idx, double **val, int64_t *live, double *dead_sq);

@@ -63,8 +63,9 @@ def sparsity(ctx):
     return zeros / total
 
 
-def run(ctx, iterations, schedule=None, tol=None, log=None, compact_every=5):
-    """Alg. 2 on a VestContext: factor sweeps, core sweep, RE, maybe prune.
+def run(ctx, iterations, schedule=None, tol=None, log=None, compact_every=5, normalize=True):
+    """Alg. 2 on a VestContext: factor sweeps, core sweep, RE, maybe prune,
+    and at the end the column normalisation (normalize=True).
 
     Entries with a fully marked row are dropped from the layouts (vest_compact)
     every `compact_every` prune steps and once pruning has stopped (0 = never);
@@ -97,5 +98,7 @@ def run(ctx, iterations, schedule=None, tol=None, log=None, compact_every=5):
             log({"iter": t, "re": L["re"], "loss": L["loss"], "sparsity": sp, "pruned": pruned})
         if tol is not None and len(re_hist) > 1 and abs(re_hist[-1] - re_hist[-2]) < tol and not pruned:
             break
+    if normalize:
+        ctx.normalize()
     torch.cuda.current_stream().synchronize()
     return re_hist

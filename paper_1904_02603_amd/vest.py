@@ -21,7 +21,8 @@ FP64, FP32, BF16 = 0, 1, 2
 KERNEL_AUTO, KERNEL_DENSE, KERNEL_GATHER = 0, 1, 2
 
 EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
-           "vest_responsibility", "vest_prune", "vest_loss", "vest_compact", "vest_set_kernel",
+           "vest_responsibility", "vest_prune", "vest_loss", "vest_normalize", "vest_count_nonzeros",
+           "vest_export", "vest_test_error", "vest_value_keys", "vest_compact", "vest_set_kernel",
            "vest_layout_stats", "vest_destroy", "vest_strerror", "vest_last_error",
            "vest_server_create", "vest_server_submit", "vest_server_progress", "vest_server_status",
            "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]
@@ -69,6 +70,11 @@ def load_library(path=LIB_PATH):
     lib.vest_loss.argtypes = [vp, vp]
     lib.vest_set_kernel.argtypes = [vp, i32]
     lib.vest_compact.argtypes = [vp, C.POINTER(i64)]
+    lib.vest_normalize.argtypes = [vp]
+    lib.vest_count_nonzeros.argtypes = [vp, vp]
+    lib.vest_export.argtypes = [vp, vp, vp, vp, vp]
+    lib.vest_test_error.argtypes = [vp, vp, vp, i64, vp]
+    lib.vest_value_keys.argtypes = [vp, vp, vp]
     lib.vest_layout_stats.argtypes = [vp, i32, vp]
     lib.vest_destroy.argtypes = [vp]
     lib.vest_strerror.argtypes = [C.c_int]
@@ -86,7 +92,8 @@ def load_library(path=LIB_PATH):
                  "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]:
         getattr(lib, name).restype = C.c_int
     for name in ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
-                 "vest_responsibility", "vest_prune", "vest_loss", "vest_compact", "vest_set_kernel",
+                 "vest_responsibility", "vest_prune", "vest_loss", "vest_normalize", "vest_count_nonzeros",
+                 "vest_export", "vest_test_error", "vest_value_keys", "vest_compact", "vest_set_kernel",
                  "vest_layout_stats", "vest_destroy"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -215,6 +222,42 @@ class VestContext:
         for n in range(self.N):
             self.sweep_factor(n)
         self.sweep_core()
+
+    def normalize(self):
+        """Final column normalisation of Alg. 2 (reconstruction unchanged)."""
+        _check(self.lib.vest_normalize(self.ctx), "vest_normalize")
+
+    def count_nonzeros(self):
+        out = (C.c_int64 * (self.N + 1))()
+        _check(self.lib.vest_count_nonzeros(self.ctx, out), "vest_count_nonzeros")
+        return list(out)
+
+    def export(self):
+        """Sparse model: [(flat_idx, values) per factor], (flat_idx, values) of the core."""
+        cnt = self.count_nonzeros()
+        fi = [torch.empty(max(c, 1), dtype=torch.int64, device=self.core.device) for c in cnt[:-1]]
+        fv = [torch.empty(max(c, 1), dtype=torch.float64, device=self.core.device) for c in cnt[:-1]]
+        ci = torch.empty(max(cnt[-1], 1), dtype=torch.int64, device=self.core.device)
+        cv = torch.empty(max(cnt[-1], 1), dtype=torch.float64, device=self.core.device)
+        _check(self.lib.vest_export(self.ctx, _ptr_array(fi), _ptr_array(fv), _ptr(ci), _ptr(cv)), "vest_export")
+        torch.cuda.synchronize()
+        return [(a[:c], b[:c]) for a, b, c in zip(fi, fv, cnt)], (ci[:cnt[-1]], cv[:cnt[-1]])
+
+    def test_error(self, idx, val):
+        """(sum (X-B)^2, sum X^2, RE) of the current model on held-out entries."""
+        i = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device=self.core.device)
+        v = torch.as_tensor(np.ascontiguousarray(val, dtype=np.float64), device=self.core.device)
+        out = (C.c_double * 3)()
+        _check(self.lib.vest_test_error(self.ctx, _ptr(i), _ptr(v), int(i.shape[0]), out), "vest_test_error")
+        return {"sse": out[0], "xnorm2": out[1], "re": out[2]}
+
+    def value_keys(self):
+        """Magnitude keys (value-pruning comparator); the next prune uses them."""
+        self.core_key = torch.empty_like(self.core)
+        self.factor_keys = [torch.empty_like(f) for f in self.factors]
+        _check(self.lib.vest_value_keys(self.ctx, _ptr(self.core_key), _ptr_array(self.factor_keys)),
+               "vest_value_keys")
+        return self.core_key, self.factor_keys
 
     def compact(self):
         """Drop entries with a fully marked row in some mode; returns the kept count."""
