@@ -136,8 +136,7 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     c->stage_bytes = (size_t)((char *)c->ms - (char *)c->e) + ms_bytes;
     c->hdiag = (double *)take(c->G * 8);
     for (int n = 0; n < N; ++n) c->Gp[n] = take(c->G * ts);
-    for (int n = 0; n < N; ++n)
-        c->A32[n] = c->f32 ? (float *)take(c->d.dims[n] * J * 4) : nullptr;
+    for (int n = 0; n < N; ++n) c->Ag[n] = take(c->d.dims[n] * gather_ld(J, (int)ts) * ts);
     for (int m = 0; m + 2 < N; ++m) c->colA[m] = take(c->d.dims[m] * J * ts);
     const int gw = gram_width(J);
     const int64_t Il = c->d.dims[N - 1];
@@ -203,13 +202,12 @@ static int refresh_gp(vest_ctx *c)
     return VEST_OK;
 }
 
-static int ensure_a32(vest_ctx *c)
+static int ensure_ag(vest_ctx *c)
 {
-    if (!c->f32) return VEST_OK;
     for (int n = 0; n < c->N; ++n)
-        if (!c->a32_valid[n]) {
-            CALL_HIP(c, launch_cast_factor(c, n), "cast factor");
-            c->a32_valid[n] = true;
+        if (!c->ag_valid[n]) {
+            CALL_HIP(c, launch_gather_copy(c, n), "gather copy");
+            c->ag_valid[n] = true;
         }
     return VEST_OK;
 }
@@ -217,7 +215,7 @@ static int ensure_a32(vest_ctx *c)
 static int ensure_residual(vest_ctx *c)
 {
     if (c->e_valid && c->ms_valid) return VEST_OK;
-    int rc = ensure_a32(c);
+    int rc = ensure_ag(c);
     if (rc) return rc;
     rc = ensure_gp(c, c->N - 1);
     if (rc) return rc;
@@ -349,8 +347,8 @@ int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const dou
     for (int n = 0; n < c->N; ++n) c->marked_fac[n] = hc[n];
     c->marked_core = hc[c->N];
     c->core_version = 1;
-    for (int n = 0; n < c->N; ++n) c->a32_valid[n] = false;
-    if ((rc = ensure_a32(c)) || (rc = refresh_gp(c))) { delete c; return rc; }
+    for (int n = 0; n < c->N; ++n) c->ag_valid[n] = false;
+    if ((rc = ensure_ag(c)) || (rc = refresh_gp(c))) { delete c; return rc; }
     *out = c;
     return VEST_OK;
 }
@@ -360,7 +358,7 @@ int vest_sweep_factor(vest_ctx *c, int32_t mode)
     int rc = live(c);
     if (rc) return rc;
     if (mode < 0 || mode >= c->N) { set_error("mode %d outside 0..%d", mode, c->N - 1); return VEST_EINVAL; }
-    if ((rc = ensure_a32(c))) return rc;
+    if ((rc = ensure_ag(c))) return rc;
     if ((rc = ensure_gp(c, mode))) return rc;
     CALL_HIP(c, launch_rowgroup(c, mode, OP_SWEEP), "factor sweep");
     c->e_valid = false;
@@ -421,13 +419,13 @@ int vest_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
         if (factor_k[n] > 0) {
             CALL_HIP(c, launch_prune(c, n, factor_k[n]), "prune factor");
             c->marked_fac[n] += factor_k[n];
-            c->a32_valid[n] = false;
+            c->ag_valid[n] = false;
             c->ms_valid = false;
             c->hdiag_valid = false;
         }
     c->e_valid = false;
     c->keys_pending = false;
-    if ((rc = ensure_a32(c))) return rc;
+    if ((rc = ensure_ag(c))) return rc;
     return refresh_gp(c);
 }
 
@@ -481,12 +479,12 @@ int vest_normalize(vest_ctx *c)
     if (rc) return rc;
     CALL_HIP(c, launch_normalize(c), "normalisation");
     c->core_version++;
-    for (int n = 0; n < c->N; ++n) c->a32_valid[n] = false;
+    for (int n = 0; n < c->N; ++n) c->ag_valid[n] = false;
     c->e_valid = false;
     c->ms_valid = false;
     c->hdiag_valid = false;
     c->keys_pending = false;
-    if ((rc = ensure_a32(c))) return rc;
+    if ((rc = ensure_ag(c))) return rc;
     return refresh_gp(c);
 }
 
@@ -520,7 +518,7 @@ int vest_test_error(vest_ctx *c, const int32_t *idx, const double *val, int64_t 
     if (n > 0) {
         for (int m = 0; m < c->N; ++m)
             if ((rc = ensure_gp(c, m))) return rc;
-        if ((rc = ensure_a32(c))) return rc;
+        if ((rc = ensure_ag(c))) return rc;
         double *dout = c->red + 16 * kLossBlocks;
         CALL_HIP(c, hipMemsetAsync(c->flags, 0, 64, c->stream), "flags");
         CALL_HIP(c, launch_heldout(c, idx, val, n, dout), "held-out error");

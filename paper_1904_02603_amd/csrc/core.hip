@@ -42,7 +42,7 @@ struct SlabArgs {
     int32_t lead[NL];             // leading core indices of this slab
     int32_t lprev[NL];            // ... of the previous slab
     const T *ms;                  // mode N-2 factor row of every slot (see ms_index)
-    const T *Alast;               // mode N-1 factor, row-major
+    const T *Alast;               // mode N-1 factor, gather copy (row stride gather_ld)
     T *e;
     const double *dprev;          // [J][J] change of the previous slab's elements
     double *rowbuf;               // [I_{N-1}][ldrb]
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
     T u[J];
     if (a.has_prev) {
         T al[J];
-        if (has_row) load_row<J, T>(a.Alast + (int64_t)row * J, al);
+        if (has_row) load_grow<J, T>(a.Alast + (int64_t)row * gather_ld(J, sizeof(T)), al);
         else
 #pragma unroll
             for (int v = 0; v < J; ++v) al[v] = T(0);
@@ -596,7 +596,6 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
 {
     const int last = N - 1;
     const ModeLayout &L = c->lay[last];
-    const bool f32 = std::is_same<T, float>::value;
     constexpr int GW = gram_width(J);
     hipStream_t st = c->stream;
     const int64_t Ilast = c->d.dims[last];
@@ -614,7 +613,7 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
         a.dimA[m] = I;
     }
     a.ms = reinterpret_cast<const T *>(c->ms);
-    a.Alast = f32 ? reinterpret_cast<const T *>(c->A32[last]) : reinterpret_cast<const T *>(c->A[last]);
+    a.Alast = reinterpret_cast<const T *>(c->Ag[last]);
     a.e = reinterpret_cast<T *>(c->e);
     a.dprev = c->dprev;
     a.rowbuf = c->rowbuf;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 #include "internal.h"
 
@@ -67,6 +68,22 @@ __device__ __forceinline__ CoreBases<T> core_bases(const T *__restrict__ Gp)
     return G;
 }
 
+// Re-launders the bases inside a loop: the core operands then count as
+// loop-variant and their loads stay at their uses instead of being hoisted
+// out of the loop (where hundreds of them would be kept live in scalar
+// registers and spilled).
+template <int N, int J, typename T>
+__device__ __forceinline__ void core_fence(CoreBases<T> &G)
+{
+    constexpr int W = CoreBases<T>::W;
+#pragma unroll
+    for (int k = 0; k < (ipow(J, N) + W - 1) / W; ++k) {
+        uint64_t q = reinterpret_cast<uint64_t>(G.b[k]);
+        asm volatile("" : "+s"(q));
+        G.b[k] = (typename CoreBases<T>::CPtr)q;
+    }
+}
+
 template <int F, typename T>
 __device__ __forceinline__ T core_at(const CoreBases<T> &G)
 {
@@ -121,6 +138,80 @@ __device__ __forceinline__ void delta_vec(const CoreBases<T> &G, const T (&r)[N 
     delta_from<N, J, 0, T>(G, r, d);
 }
 
+// The same contraction for two entries at once: every core operand is
+// loaded once and feeds both.  The core is walked in blocks of J consecutive
+// values (one innermost sum each, in the order delta_vec visits them); the
+// loads of block B + 1 are issued before block B is consumed and a
+// scheduling barrier closes every block, so the operands of at most two
+// blocks are live in scalar registers (left to itself the scheduler would
+// separate the two entries' chains and keep hundreds of operands live).
+// Each entry's terms are added in the order of delta_vec, so both results
+// equal the one-entry form bit for bit.
+template <int F, int O, int J, typename T>
+__device__ __forceinline__ void load_block(const CoreBases<T> &G, T (&out)[J])
+{
+    if constexpr (O < J) {
+        out[O] = core_at<F + O>(G);
+        load_block<F, O + 1, J, T>(G, out);
+    }
+}
+
+template <int NO, int J, int B, typename T>
+__device__ __forceinline__ void pair_step(const CoreBases<T> &G, const T (&ra)[NO][J], const T (&rb)[NO][J],
+                                          T (&buf)[2][J], T (&acca)[NO], T (&accb)[NO], T (&da)[J], T (&db)[J])
+{
+    constexpr int NB = ipow(J, NO);   // blocks of J values in the J^(NO+1) core
+    if constexpr (B + 1 < NB) load_block<(B + 1) * J, 0, J, T>(G, buf[(B + 1) & 1]);
+    const T(&cur)[J] = buf[B & 1];
+    T va = cur[0] * ra[NO - 1][0], vb = cur[0] * rb[NO - 1][0];
+#pragma unroll
+    for (int o = 1; o < J; ++o) {
+        va = vfma(cur[o], ra[NO - 1][o], va);
+        vb = vfma(cur[o], rb[NO - 1][o], vb);
+    }
+    // fold the finished innermost sum into the outer levels NO-2 .. 0
+    bool up = true;
+#pragma unroll
+    for (int L = NO - 2; L >= 0; --L) {
+        if (up) {
+            const int o = (B / ipow(J, NO - 2 - L)) % J;
+            if (o == 0) {
+                acca[L] = va * ra[L][0];
+                accb[L] = vb * rb[L][0];
+            } else {
+                acca[L] = vfma(va, ra[L][o], acca[L]);
+                accb[L] = vfma(vb, rb[L][o], accb[L]);
+            }
+            up = o == J - 1;
+            va = acca[L];
+            vb = accb[L];
+        }
+    }
+    if (up) {
+        constexpr int j = B / ipow(J, NO - 1);
+        da[j] = va;
+        db[j] = vb;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int NO, int J, typename T, int... Bs>
+__device__ __forceinline__ void pair_all(const CoreBases<T> &G, const T (&ra)[NO][J], const T (&rb)[NO][J],
+                                         T (&buf)[2][J], T (&acca)[NO], T (&accb)[NO], T (&da)[J], T (&db)[J],
+                                         std::integer_sequence<int, Bs...>)
+{
+    (pair_step<NO, J, Bs, T>(G, ra, rb, buf, acca, accb, da, db), ...);
+}
+
+template <int N, int J, typename T>
+__device__ __forceinline__ void delta_vec2(const CoreBases<T> &G, const T (&ra)[N - 1][J], const T (&rb)[N - 1][J],
+                                           T (&da)[J], T (&db)[J])
+{
+    T buf[2][J], acca[N - 1], accb[N - 1];
+    load_block<0, 0, J, T>(G, buf[0]);
+    pair_all<N - 1, J, T>(G, ra, rb, buf, acca, accb, da, db, std::make_integer_sequence<int, ipow(J, N - 1)>{});
+}
+
 // Slot-ordered copy of a per-entry factor row, interleaved per wave: the J
 // values of the 64 slots of one (wave, k) step form one contiguous block of
 // 64 J elements, value t of every lane in a 64-element run (slot bases are
@@ -154,6 +245,31 @@ __device__ __forceinline__ void load_row(const T *__restrict__ p, T (&r)[J])
     } else {
 #pragma unroll
         for (int v = 0; v < J; ++v) r[v] = p[v];
+    }
+}
+
+// Load a row of a gather copy (16-byte aligned start): 16-byte loads, then
+// the remainder in 8- and 4-byte pieces.
+template <int J, typename T>
+__device__ __forceinline__ void load_grow(const T *__restrict__ p, T (&r)[J])
+{
+    constexpr int bytes = J * (int)sizeof(T);
+    const char *q = reinterpret_cast<const char *>(__builtin_assume_aligned(p, 16));
+    char *d = reinterpret_cast<char *>(r);
+#pragma unroll
+    for (int v = 0; v < bytes / 16; ++v) {
+        const uint4 x = reinterpret_cast<const uint4 *>(q)[v];
+        __builtin_memcpy(d + 16 * v, &x, 16);
+    }
+    constexpr int o8 = bytes / 16 * 16;
+    if constexpr (bytes - o8 >= 8) {
+        const uint2 x = *reinterpret_cast<const uint2 *>(q + o8);
+        __builtin_memcpy(d + o8, &x, 8);
+    }
+    constexpr int o4 = o8 + (bytes - o8 >= 8 ? 8 : 0);
+    if constexpr (bytes - o4 >= 4) {
+        const uint32_t x = *reinterpret_cast<const uint32_t *>(q + o4);
+        __builtin_memcpy(d + o4, &x, 4);
     }
 }
 

@@ -174,9 +174,9 @@ __global__ void __launch_bounds__(256) k_heldout(const int32_t *__restrict__ idx
         }
         T r[N - 1][J];
 #pragma unroll
-        for (int m = 1; m < N; ++m) load_row<J, T>(fac.p[m] + (int64_t)ii[m] * J, r[m - 1]);
+        for (int m = 1; m < N; ++m) load_grow<J, T>(fac.p[m] + (int64_t)ii[m] * gather_ld(J, sizeof(T)), r[m - 1]);
         T own[J];
-        load_row<J, T>(fac.p[0] + (int64_t)ii[0] * J, own);
+        load_grow<J, T>(fac.p[0] + (int64_t)ii[0] * gather_ld(J, sizeof(T)), own);
         T d[J];
         delta_vec<N, J, T>(Gb, r, d);
         T b = own[0] * d[0];
@@ -234,7 +234,7 @@ static hipError_t heldout_t(vest_ctx *c, const int32_t *idx, const double *val, 
     FacIn<T> fa{};
     for (int m = 0; m < N; ++m) {
         dm.d[m] = c->d.dims[m];
-        fa.p[m] = c->f32 ? reinterpret_cast<const T *>(c->A32[m]) : reinterpret_cast<const T *>(c->A[m]);
+        fa.p[m] = reinterpret_cast<const T *>(c->Ag[m]);
     }
     const int nb = kLossBlocks;
     hipLaunchKernelGGL((k_heldout<N, J, T>), dim3(nb), dim3(256), 0, c->stream, idx, val, n, dm, fa,

@@ -108,6 +108,15 @@ __host__ __device__ constexpr int keys_nacc(int N, int J)
     return 2 * J * key_slabs(N, J, true) > J * key_slabs(N, J, false) ? 2 * J * key_slabs(N, J, true)
                                                                       : J * key_slabs(N, J, false);
 }
+// Row stride (elements) of the gather copies of the factors: the row's bytes
+// rounded up to a power of two (at least 16), so that with a 256-byte aligned
+// base no row straddles a 128-byte cache line and a random row costs one line.
+__host__ __device__ constexpr int gather_ld(int J, int tsize)
+{
+    int b = 16;
+    while (b < J * tsize) b *= 2;
+    return b / tsize;
+}
 __host__ __device__ constexpr int rowbuf_width(int N, int J)
 {
     return gram_width(J) > keys_width(N, J) ? gram_width(J) : keys_width(N, J);
@@ -138,7 +147,7 @@ struct vest_ctx {
     void *ms = nullptr;               // mode N-2 factor row of every core-layout slot (T)
     double *hdiag = nullptr;          // diagonal of every slab's Gram matrix [|G|]
     void *Gp[VEST_MAX_ORDER] = {};    // core permuted for each mode (T)
-    float *A32[VEST_MAX_ORDER] = {};  // FP32 copies of the factors (FP32 form)
+    void *Ag[VEST_MAX_ORDER] = {};    // gather copies of the factors (T, row stride gather_ld)
     void *colA[VEST_MAX_ORDER] = {};  // column-major factor copies, modes < N-2 (T)
     double *rowbuf = nullptr;         // [I_{N-1}][ldrb]
     int ldrb = 0;
@@ -166,7 +175,7 @@ struct vest_ctx {
     int64_t marked_fac[VEST_MAX_ORDER] = {};
     uint64_t core_version = 1;
     uint64_t gp_version[VEST_MAX_ORDER] = {};
-    bool a32_valid[VEST_MAX_ORDER] = {};
+    bool ag_valid[VEST_MAX_ORDER] = {};
     bool e_valid = false;
     bool ms_valid = false;            // ms matches the current factors
     bool hdiag_valid = false;         // hdiag matches the current factors
@@ -194,7 +203,7 @@ hipError_t launch_value_keys(vest_ctx *c, double *core_key, double *const *fkey)
 hipError_t launch_compact(vest_ctx *c, int32_t **idx, double **val, int64_t *live, double *dead_sq);
 hipError_t launch_core_keys(vest_ctx *c, double *core_key);
 hipError_t launch_permute_core(vest_ctx *c, int mode);
-hipError_t launch_cast_factor(vest_ctx *c, int mode);
+hipError_t launch_gather_copy(vest_ctx *c, int mode);
 hipError_t launch_loss(vest_ctx *c, double *dev_out3);          // sse, reg (device)
 hipError_t launch_prune(vest_ctx *c, int tensor, int64_t k);     // tensor -1 = core
 hipError_t launch_sumsq(hipStream_t s, const double *v, int64_t n, double *partial, double *out);

@@ -52,17 +52,30 @@ hipError_t launch_permute_core(vest_ctx *c, int mode)
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_cast(const double *__restrict__ a, int64_t n, float *__restrict__ out)
+// Gather copy of a factor: rows of J values at stride ld in the compute type,
+// the padding zeroed.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gcopy(const double *__restrict__ a, int64_t rows, int J, int ld,
+                                               T *__restrict__ out)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) out[q] = (float)a[q];
+    if (q >= rows * ld) return;
+    const int64_t r = q / ld;
+    const int j = (int)(q - r * ld);
+    out[q] = j < J ? (T)a[r * J + j] : T(0);
 }
 
-hipError_t launch_cast_factor(vest_ctx *c, int mode)
+hipError_t launch_gather_copy(vest_ctx *c, int mode)
 {
-    const int64_t n = c->d.dims[mode] * c->J;
-    hipLaunchKernelGGL(k_cast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->A[mode], n,
-                       c->A32[mode]);
+    const int64_t rows = c->d.dims[mode];
+    const int ld = gather_ld(c->J, c->tsize);
+    const unsigned blocks = (unsigned)((rows * ld + 255) / 256);
+    if (c->f32)
+        hipLaunchKernelGGL(k_gcopy<float>, dim3(blocks), dim3(256), 0, c->stream, c->A[mode], rows, c->J, ld,
+                           reinterpret_cast<float *>(c->Ag[mode]));
+    else
+        hipLaunchKernelGGL(k_gcopy<double>, dim3(blocks), dim3(256), 0, c->stream, c->A[mode], rows, c->J, ld,
+                           reinterpret_cast<double *>(c->Ag[mode]));
     return hipGetLastError();
 }
 

@@ -34,9 +34,8 @@ struct RowArgs {
     const T *xval;
     const T *fac[N - 1];      // other modes, ascending, compute type
     const uint32_t *omask[N - 1];  // their marking tables (gather form)
-    const T *own;             // mode-n factor in compute type (OP_RESID)
+    T *Ag;                    // mode-n gather copy (stride gather_ld): own rows; OP_SWEEP refreshes it
     double *A;                // mode-n FP64 factor
-    float *A32;               // FP32 copy refreshed by OP_SWEEP (may be null)
     const uint32_t *mask;     // mode-n marking table
     double *partials;         // long-row chunk partials
     T *e;                     // OP_RESID: out
@@ -67,11 +66,9 @@ __device__ __forceinline__ void row_epilogue(const RowArgs<N, J, T> &a, int row,
         double *dst = a.A + (int64_t)row * J;
 #pragma unroll
         for (int j = 0; j < J; ++j) dst[j] = av[j];
-        if (a.A32) {
-            float *d32 = a.A32 + (int64_t)row * J;
+        T *dg = a.Ag + (int64_t)row * gather_ld(J, sizeof(T));
 #pragma unroll
-            for (int j = 0; j < J; ++j) d32[j] = (float)av[j];
-        }
+        for (int j = 0; j < J; ++j) dg[j] = (T)av[j];
     } else {
         // Delta(a_ij) = sum (2 e + a delta_j) a delta_j = 2 a s_j + a^2 q_j
         double *dst = a.keys + (int64_t)row * J;
@@ -145,7 +142,7 @@ __device__ __forceinline__ void delta_gather(const T *__restrict__ Gt, const uin
     if (!live) return;
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
-        load_row<J, T>(fac[k] + (int64_t)ii[k] * J, r[k]);
+        load_grow<J, T>(fac[k] + (int64_t)ii[k] * gather_ld(J, sizeof(T)), r[k]);
         uint32_t b = 0;
 #pragma unroll
         for (int t = 0; t < J; ++t) b |= (r[k][t] != T(0) ? 1u : 0u) << t;
@@ -182,6 +179,89 @@ __device__ __forceinline__ void stage_core(const T *__restrict__ Gp, T *Gt, uint
     __syncthreads();
 }
 
+// Dense OP_KEYS / OP_RESID steps, two entries per lane at a time (steps k
+// and k + 1 of the lane's slice): one pass over the core operands serves both
+// contractions (delta_vec2).  Padding slots and the missing partner of an odd
+// last step are computed on row 0 and masked out of the results by selects;
+// the statistics take the entries in slot order, as the one-entry loop does.
+// The indices and values of the next pair are loaded ahead.
+template <int N, int J, typename T, int OP>
+__device__ __forceinline__ void pair_steps(const RowArgs<N, J, T> &a, const CoreBases<T> &Gb, const WaveInfo &wi,
+                                           int lane, const T (&own)[J], T (&s)[row_nacc<J, OP>()])
+{
+    const int K = wi.K;
+    int32_t ia[N - 1], ib[N - 1];
+    T xa = T(0), xb = T(0);
+    auto load_pair = [&](int k, int32_t (&i0)[N - 1], T &x0, int32_t (&i1)[N - 1], T &x1) {
+        const int64_t s0 = wi.base + (int64_t)(k < K ? k : K - 1) * kWave + lane;
+        const int64_t s1 = wi.base + (int64_t)(k + 1 < K ? k + 1 : K - 1) * kWave + lane;
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) {
+            i0[m] = a.oidx[m][s0];
+            i1[m] = a.oidx[m][s1];
+        }
+        x0 = a.xval[s0];
+        x1 = a.xval[s1];
+    };
+    if (K > 0) load_pair(0, ia, xa, ib, xb);
+#pragma unroll 1
+    for (int k = 0; k < K; k += 2) {
+        const int64_t sla = wi.base + (int64_t)k * kWave + lane;
+        const int64_t slb = sla + kWave;
+        const bool hb = k + 1 < K;
+        int32_t na[N - 1], nb[N - 1];
+        T nxa, nxb;
+        load_pair(k + 2, na, nxa, nb, nxb);
+        const bool oka = ia[0] >= 0, okb = hb && ib[0] >= 0;
+        T ra[N - 1][J], rb[N - 1][J];
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) {
+            load_grow<J, T>(a.fac[m] + (int64_t)(oka ? ia[m] : 0) * gather_ld(J, sizeof(T)), ra[m]);
+            load_grow<J, T>(a.fac[m] + (int64_t)(okb ? ib[m] : 0) * gather_ld(J, sizeof(T)), rb[m]);
+        }
+        T da[J], db[J];
+        CoreBases<T> G = Gb;
+        core_fence<N, J, T>(G);
+        delta_vec2<N, J, T>(G, ra, rb, da, db);
+        T ba = own[0] * da[0], bb = own[0] * db[0];
+#pragma unroll
+        for (int t = 1; t < J; ++t) {
+            ba = vfma(own[t], da[t], ba);
+            bb = vfma(own[t], db[t], bb);
+        }
+        const T ea = oka ? xa - ba : T(0), eb = okb ? xb - bb : T(0);
+        if constexpr (OP == OP_KEYS) {
+#pragma unroll
+            for (int t = 0; t < J; ++t) {
+                const T ua = oka ? da[t] : T(0), ub = okb ? db[t] : T(0);
+                s[t] = vfma(ea, ua, s[t]);
+                s[t] = vfma(eb, ub, s[t]);
+                s[J + t] = vfma(ua, ua, s[J + t]);
+                s[J + t] = vfma(ub, ub, s[J + t]);
+            }
+        } else {
+            // without a partner the second store repeats the first (same
+            // lane, same values), so both contractions stay unconditional
+            const int64_t slc = hb ? slb : sla;
+            a.e[sla] = ea;
+            a.e[slc] = hb ? eb : ea;
+#pragma unroll
+            for (int t = 0; t < J; ++t) {
+                const T va = oka ? ra[N - 2][t] : T(0), vb = okb ? rb[N - 2][t] : T(0);
+                a.ms[ms_index<J>(sla, t)] = va;
+                a.ms[ms_index<J>(slc, t)] = hb ? vb : va;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) {
+            ia[m] = na[m];
+            ib[m] = nb[m];
+        }
+        xa = nxa;
+        xb = nxb;
+    }
+}
+
 // GA = false: dense factored contraction, core operands as scalar loads.
 // GA = true : pruned-phase gather contraction from LDS (dynamic LDS of
 //             gather_lds_bytes<N, J, T>() bytes).
@@ -204,7 +284,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 
     T own[J];
     if constexpr (OP == OP_RESID || OP == OP_KEYS) {
-        if (has_row) load_row<J, T>(a.own + (int64_t)row * J, own);
+        if (has_row) load_grow<J, T>(a.Ag + (int64_t)row * gather_ld(J, sizeof(T)), own);
         else
 #pragma unroll
             for (int j = 0; j < J; ++j) own[j] = T(0);
@@ -213,6 +293,9 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
+    if constexpr (!GA && OP != OP_SWEEP) {
+        pair_steps<N, J, T, OP>(a, Gb, wi, lane, own, s);
+    } else {
     // Software pipeline: the indices and value of step k + 1 (gather form:
     // k + 2) are loaded at the top of step k, and in the gather form the
     // marking words of step k + 1 as well, so a step waits for one memory
@@ -263,11 +346,12 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
                 if constexpr (OP == OP_RESID) {
                     // the slot copy of the mode N-2 row must hold the values
                     // even when delta vanished without loading them
-                    load_row<J, T>(a.fac[N - 2] + (int64_t)ci[N - 2] * J, r[N - 2]);
+                    load_grow<J, T>(a.fac[N - 2] + (int64_t)ci[N - 2] * gather_ld(J, sizeof(T)), r[N - 2]);
                 }
             } else {
 #pragma unroll
-                for (int m = 0; m < N - 1; ++m) load_row<J, T>(a.fac[m] + (int64_t)ci[m] * J, r[m]);
+                for (int m = 0; m < N - 1; ++m)
+                    load_grow<J, T>(a.fac[m] + (int64_t)ci[m] * gather_ld(J, sizeof(T)), r[m]);
                 delta_vec<N, J, T>(Gb, r, d);
             }
             const T x = cx;
@@ -310,6 +394,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
             for (int m = 0; m < N - 1; ++m) ci[m] = ni[m];
             cx = nx;
         }
+    }
     }
     if constexpr (OP == OP_RESID) {
         return;
@@ -436,8 +521,8 @@ __global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, c
         const int32_t i1 = a.oidx[1][sl];  // 0 on padding slots
         const bool ok = i0 >= 0;
         float rp[J], rq[J];
-        load_row<J, float>(a.fac[0] + (int64_t)(ok ? i0 : 0) * J, rp);
-        load_row<J, float>(a.fac[1] + (int64_t)i1 * J, rq);
+        load_grow<J, float>(a.fac[0] + (int64_t)(ok ? i0 : 0) * gather_ld(J, 4), rp);
+        load_grow<J, float>(a.fac[1] + (int64_t)i1 * gather_ld(J, 4), rq);
 #pragma unroll
         for (int t = 0; t < J; ++t) rq[t] = ok ? rq[t] : 0.0f;  // zero column: T = 0, delta = 0
         const float x = a.xval[sl];                               // 0 on padding slots
@@ -561,14 +646,13 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     for (int k = 0; k < N; ++k) {
         if (k == mode) continue;
         a.oidx[m] = L.oidx[m];
-        a.fac[m] = f32 ? reinterpret_cast<const T *>(c->A32[k]) : reinterpret_cast<const T *>(c->A[k]);
+        a.fac[m] = reinterpret_cast<const T *>(c->Ag[k]);
         a.omask[m] = c->fmask[k];
         ++m;
     }
     a.xval = reinterpret_cast<const T *>(L.xval);
-    a.own = f32 ? reinterpret_cast<const T *>(c->A32[mode]) : reinterpret_cast<const T *>(c->A[mode]);
+    a.Ag = reinterpret_cast<T *>(c->Ag[mode]);
     a.A = c->A[mode];
-    a.A32 = f32 ? c->A32[mode] : nullptr;
     a.mask = c->fmask[mode];
     a.partials = c->partials;
     a.e = reinterpret_cast<T *>(c->e);
