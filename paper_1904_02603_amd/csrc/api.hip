@@ -140,10 +140,10 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     for (int m = 0; m + 2 < N; ++m) c->colA[m] = take(c->d.dims[m] * J * ts);
     const int gw = gram_width(J);
     const int64_t Il = c->d.dims[N - 1];
-    c->ldrb = rowbuf_width(N, J);
-    const int64_t gsq = (int64_t)gw * gw > (int64_t)keys_width(N, J) * round8(2 * J)
+    c->ldrb = rowbuf_width(N, J, (int)ts);
+    const int64_t gsq = (int64_t)gw * gw > (int64_t)keys_width(N, J, (int)ts) * round8(2 * J)
                             ? (int64_t)gw * gw
-                            : (int64_t)keys_width(N, J) * round8(2 * J);
+                            : (int64_t)keys_width(N, J, (int)ts) * round8(2 * J);
     // (keys_width x round8(2J) also bounds the R-only batches: round8(J S) x round8(J))
     c->rowbuf = (double *)take(Il * c->ldrb * 8);
     c->kp = (double *)take(Il * gw * 8);
@@ -151,7 +151,7 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     c->gram = (double *)take(gsq * 8);
     c->dprev = (double *)take(J * J * 8);
     int na = nacc_vc(J) > 2 * J ? nacc_vc(J) : 2 * J;
-    na = na > keys_nacc(N, J) ? na : keys_nacc(N, J);
+    na = na > keys_nacc(N, J, (int)ts) ? na : keys_nacc(N, J, (int)ts);
     c->partials = (double *)take(p.chunk_bound * na * 8);
     c->red = (double *)take((16 * kLossBlocks + 64) * 8);
     c->flags = (int32_t *)take(64);

@@ -48,7 +48,7 @@ struct SlabArgs {
     double *rowbuf;               // [I_{N-1}][ldrb]
     int32_t ldrb;
     double *partials;
-    int32_t blead[kKeyAcc * NL];  // k_slabkeys: leading indices of each slab of the batch
+    int32_t blead[kKeyAccMax * NL];  // k_slabkeys: leading indices of each slab of the batch
 };
 
 // The mode N-2 factor row of every entry is read from the slot-ordered copy
@@ -209,20 +209,21 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
             for (int t = 0; t < J; ++t) mq[t] = ok ? mv[q][t] : T(0);
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
-                if (b >= nsb) break;
-                T p = T(1);
+                if (b < nsb) {   // (no early exit: the accumulator indices stay compile-time)
+                    T p = T(1);
 #pragma unroll
-                for (int m = 0; m < N - 2; ++m) {
-                    const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
-                    p *= a.colA[m][(int64_t)a.blead[b * NL + m] * a.dimA[m] + i];
-                }
-                const T ep = evq * p;
+                    for (int m = 0; m < N - 2; ++m) {
+                        const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
+                        p *= a.colA[m][(int64_t)a.blead[b * NL + m] * a.dimA[m] + i];
+                    }
+                    const T ep = evq * p;
 #pragma unroll
-                for (int t = 0; t < J; ++t) {
-                    s[b * PER + t] = vfma(ep, mq[t], s[b * PER + t]);
-                    if constexpr (WITH_D) {
-                        const T w = p * mq[t];
-                        s[b * PER + J + t] = vfma(w, w, s[b * PER + J + t]);
+                    for (int t = 0; t < J; ++t) {
+                        s[b * PER + t] = vfma(ep, mq[t], s[b * PER + t]);
+                        if constexpr (WITH_D) {
+                            const T w = p * mq[t];
+                            s[b * PER + J + t] = vfma(w, w, s[b * PER + J + t]);
+                        }
                     }
                 }
             }
@@ -557,7 +558,7 @@ __global__ void __launch_bounds__(256) k_corekeys(const double *__restrict__ P, 
 template <int N, int J, typename T, bool WITH_D>
 static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out)
 {
-    constexpr int SB = key_slabs(N, J, WITH_D);
+    constexpr int SB = key_slabs(N, J, WITH_D, (int)sizeof(T));
     constexpr int PER = WITH_D ? 2 * J : J;
     constexpr int W1 = round8(PER * SB), W2 = round8(2 * J);   // kp2 rows are [a | a^2] in both forms
     const ModeLayout &L = c->lay[N - 1];

@@ -88,25 +88,28 @@ __host__ __device__ constexpr int gram_width(int J) { return round8(nacc_vc(J));
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
-// Core-key passes handle key_slabs(N, J, d) slabs at once (J or 2 J
-// accumulators each, at most kKeyAcc per lane so that nothing spills, never
-// more than the J^(N-2) slabs there are).
-constexpr int kKeyAcc = 64;
-__host__ __device__ constexpr int key_slabs(int N, int J, bool with_d)
+// Core-key passes handle key_slabs(N, J, d, tsize) slabs at once (J or 2 J
+// accumulators each, at most key_acc(tsize) per lane so that nothing spills,
+// never more than the J^(N-2) slabs there are): 64 FP64 or 128 FP32 values.
+constexpr int kKeyAccMax = 128;
+__host__ __device__ constexpr int key_acc(int tsize) { return tsize == 4 ? 128 : 64; }
+__host__ __device__ constexpr int key_slabs(int N, int J, bool with_d, int tsize)
 {
-    return kKeyAcc / ((with_d ? 2 : 1) * J) < 1 ? 1
-           : (kKeyAcc / ((with_d ? 2 : 1) * J) > ipow(J, N - 2) ? ipow(J, N - 2) : kKeyAcc / ((with_d ? 2 : 1) * J));
+    return key_acc(tsize) / ((with_d ? 2 : 1) * J) < 1 ? 1
+           : (key_acc(tsize) / ((with_d ? 2 : 1) * J) > ipow(J, N - 2) ? ipow(J, N - 2)
+                                                                       : key_acc(tsize) / ((with_d ? 2 : 1) * J));
 }
-__host__ __device__ constexpr int keys_width(int N, int J)
+__host__ __device__ constexpr int keys_width(int N, int J, int tsize)
 {
-    return round8(2 * J * key_slabs(N, J, true)) > round8(J * key_slabs(N, J, false))
-               ? round8(2 * J * key_slabs(N, J, true))
-               : round8(J * key_slabs(N, J, false));
+    return round8(2 * J * key_slabs(N, J, true, tsize)) > round8(J * key_slabs(N, J, false, tsize))
+               ? round8(2 * J * key_slabs(N, J, true, tsize))
+               : round8(J * key_slabs(N, J, false, tsize));
 }
-__host__ __device__ constexpr int keys_nacc(int N, int J)
+__host__ __device__ constexpr int keys_nacc(int N, int J, int tsize)
 {
-    return 2 * J * key_slabs(N, J, true) > J * key_slabs(N, J, false) ? 2 * J * key_slabs(N, J, true)
-                                                                      : J * key_slabs(N, J, false);
+    return 2 * J * key_slabs(N, J, true, tsize) > J * key_slabs(N, J, false, tsize)
+               ? 2 * J * key_slabs(N, J, true, tsize)
+               : J * key_slabs(N, J, false, tsize);
 }
 // Row stride (elements) of the gather copies of the factors: the row's bytes
 // rounded up to a power of two (at least 16), so that with a 256-byte aligned
@@ -117,9 +120,9 @@ __host__ __device__ constexpr int gather_ld(int J, int tsize)
     while (b < J * tsize) b *= 2;
     return b / tsize;
 }
-__host__ __device__ constexpr int rowbuf_width(int N, int J)
+__host__ __device__ constexpr int rowbuf_width(int N, int J, int tsize)
 {
-    return gram_width(J) > keys_width(N, J) ? gram_width(J) : keys_width(N, J);
+    return gram_width(J) > keys_width(N, J, tsize) ? gram_width(J) : keys_width(N, J, tsize);
 }
 
 }  // namespace vest
