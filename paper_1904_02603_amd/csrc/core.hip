@@ -95,16 +95,27 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
+    // the leading indices of the next batch are loaded one batch ahead, so the
+    // column gathers they address need not wait for them
+    int32_t ii[U][NI];
+    auto load_idx = [&](int k0, int32_t (&dst)[U][NI]) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
+#pragma unroll
+            for (int m = 0; m < NI; ++m) dst[q][m] = a.oidx[m][wi.base + (int64_t)kk * kWave + lane];
+        }
+    };
+    if (wi.K > 0) load_idx(0, ii);
     for (int k0 = 0; k0 < wi.K; k0 += U) {
         int64_t sl[U];
-        int32_t ii[U][NI];
+        int32_t ni[U][NI];
         T mv[U][J], ev[U];
+        load_idx(k0 + U, ni);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
             sl[q] = wi.base + (int64_t)kk * kWave + lane;
-#pragma unroll
-            for (int m = 0; m < NI; ++m) ii[q][m] = a.oidx[m][sl[q]];
             ev[q] = a.e[sl[q]];
 #pragma unroll
             for (int t = 0; t < J; ++t) mv[q][t] = a.ms[ms_index<J>(sl[q], t)];
@@ -149,6 +160,10 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
                 }
             }
         }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int m = 0; m < NI; ++m) ii[q][m] = ni[q][m];
     }
     if constexpr (ACC) {
         group_reduce<NA, T>(s, wi.glog);
@@ -186,16 +201,25 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
     T s[NA];
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
+    int32_t ii[U][NI];   // leading indices, one batch ahead (as in k_slab)
+    auto load_idx = [&](int k0, int32_t (&dst)[U][NI]) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
+#pragma unroll
+            for (int m = 0; m < NI; ++m) dst[q][m] = a.oidx[m][wi.base + (int64_t)kk * kWave + lane];
+        }
+    };
+    if (wi.K > 0) load_idx(0, ii);
     for (int k0 = 0; k0 < wi.K; k0 += U) {
         int64_t sl[U];
-        int32_t ii[U][NI];
+        int32_t ni[U][NI];
         T mv[U][J], ev[U];
+        load_idx(k0 + U, ni);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
             sl[q] = wi.base + (int64_t)kk * kWave + lane;
-#pragma unroll
-            for (int m = 0; m < NI; ++m) ii[q][m] = a.oidx[m][sl[q]];
             ev[q] = a.e[sl[q]];
 #pragma unroll
             for (int t = 0; t < J; ++t) mv[q][t] = a.ms[ms_index<J>(sl[q], t)];
@@ -228,6 +252,10 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
                 }
             }
         }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int m = 0; m < NI; ++m) ii[q][m] = ni[q][m];
     }
     group_reduce<NA, T>(s, wi.glog);
     if (wi.chunk >= 0) {
