@@ -42,6 +42,20 @@ def sweep_flops_per_entry(N, J):
     return 2 * sum(J ** m for m in range(2, N + 1)) + J * (J + 1) + 2 * J
 
 
+def slab_bytes_per_launch(N, J, nnz, dims, ts):
+    """Algorithmic HBM bytes of one slab pass of the core sweep, averaged over
+    the J^(N-2) passes of a sweep: per entry the residual (read; written by
+    every pass but the first), the slot copy of the mode N-2 row (J values) and
+    the N-2 leading indices; once per pass the per-row statistics of the last
+    mode (J + J(J+1)/2 FP64 values), that mode's factor rows and the two
+    leading-factor columns."""
+    nslab = J ** (N - 2)
+    per_entry = ts + J * ts + 4 * (N - 2) + ts * (nslab - 1) / nslab
+    rows = dims[N - 1]
+    once = rows * (J + J * (J + 1) // 2) * 8 + rows * J * ts + sum(2 * d * ts for d in dims[:N - 2])
+    return nnz * per_entry + once
+
+
 def run_leg(p, precision, steps, warmup, target):
     import torch
     from paper_1904_02603_amd import vest
@@ -90,6 +104,7 @@ def run_leg(p, precision, steps, warmup, target):
     for _ in range(warmup):
         t += 1
         step(t, False)
+    ctx.slab_timing(True)   # events around every slab pass of the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     re = None
@@ -98,13 +113,20 @@ def run_leg(p, precision, steps, warmup, target):
         re = step(t, True)["re"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    slab_total, slab_n = ctx.slab_time()
+    ctx.slab_timing(False)
     ms = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in events.items() if v}
     ms_step = elapsed * 1e3 / steps
     J = ctx.J
     fl = sweep_flops_per_entry(N, J) * nnz
     sweep_ms = sum(ms["sweep_factor_%d" % n] for n in range(N)) / N
+    dims = [int(f.shape[0]) for f in ctx.factors]
+    ts = 8 if precision == vest.FP64 else 4
     ctx.close()
     return {
+        "slab_kernel_ms": slab_total / max(1, slab_n),
+        "slab_launches": slab_n,
+        "slab_bytes_per_launch": slab_bytes_per_launch(N, J, nnz, dims, ts),
         "ms_per_step": ms_step,
         "value": N * nnz / (ms_step / 1e3),
         "sweep_only_value": N * nnz / (sweep_ms * N / 1e3),
@@ -283,21 +305,32 @@ def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
             "iterations_per_job": 10}
 
 
-def measured_traffic():
-    """Calibrated HBM bytes per launch of the factor-sweep kernel from the
-    committed counter summary, or None if the kernel changed since."""
+TRAFFIC = {   # committed counter summary and the sources of the kernel it measured
+    "slab": ("traffic_k_slab_planted-1e5^3-nnz1e7-r10_fp64.md", ["core.hip", "device.h", "internal.h"]),
+    "sweep": ("traffic_k_rowgroup_sweep_planted-1e5^3-nnz1e7-r10_fp64.md", ["rowgroup.hip", "device.h", "internal.h"]),
+}
+
+
+def source_hash(files):
     import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_1904_02603_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch of a kernel from its committed counter
+    summary, or None if the kernel's sources changed since."""
     import re
-    path = os.path.join(ROOT, "profiles", "traffic_k_rowgroup_sweep_planted-1e5^3-nnz1e7-r10_fp64.md")
+    name, files = TRAFFIC[kernel]
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    h = hashlib.sha256()
-    for f in ["rowgroup.hip", "device.h", "internal.h"]:
-        h.update(open(os.path.join(ROOT, "paper_1904_02603_amd", "csrc", f), "rb").read())
     m = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", txt)
     s = re.search(r"source-sha256: ([0-9a-f]+)", txt)
-    if not m or not s or s.group(1) != h.hexdigest()[:16]:
+    if not m or not s or s.group(1) != source_hash(files):
         return None
     return float(m.group(1))
 
@@ -420,6 +453,8 @@ def main():
         cpu = cpu_baseline(p, args.cpu_seconds)
 
     achieved = f64["sweep_flops_per_launch"] / (f64["sweep_kernel_ms"] / 1e3) / 1e12
+    slab_gbs = f64["slab_bytes_per_launch"] / (f64["slab_kernel_ms"] / 1e3) / 1e9
+    named = args.workload == DEFAULT_WORKLOAD and args.nnz is None
     out = {
         "metric": METRIC,
         "value": f64["value"],
@@ -437,12 +472,18 @@ def main():
                    "ranks": [J] * N, "reg": "L_F" if p["reg"] == 0 else "L_1", "lambda": p["lam"],
                    "step": "factor sweeps (all modes) + core sweep + loss + responsibility + prune",
                    "prune": "manual ramp min(0.01 t, 0.1) toward %.2f" % args.target},
-        "roofline": {"kernel": "k_rowgroup<OP_SWEEP> (factor sweep, one mode)", "bound": "alu",
-                     "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["f64"],
-                     "traffic": measured_traffic() if args.workload == DEFAULT_WORKLOAD and args.nnz is None else None,
-                     "flops_per_launch": f64["sweep_flops_per_launch"],
-                     "avg_launch_ms": f64["sweep_kernel_ms"]},
+        # the kernel with the largest share of the step: J^(N-2) slab passes per core sweep
+        "roofline": {"kernel": "k_slab (slab pass of the core sweep)", "bound": "hbm",
+                     "achieved": slab_gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": slab_gbs / HBM_PEAK,
+                     "traffic": measured_traffic("slab") if named else None,
+                     "bytes_per_launch": f64["slab_bytes_per_launch"],
+                     "avg_launch_ms": f64["slab_kernel_ms"], "launches_timed": f64["slab_launches"]},
+        "roofline_sweep": {"kernel": "k_rowgroup<OP_SWEEP> (factor sweep, one mode)", "bound": "alu",
+                           "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
+                           "frac": achieved / PEAK["f64"],
+                           "traffic": measured_traffic("sweep") if named else None,
+                           "flops_per_launch": f64["sweep_flops_per_launch"],
+                           "avg_launch_ms": f64["sweep_kernel_ms"]},
         "cpu_baseline": cpu,
         "breakdown_ms": f64["breakdown_ms"],
         "sweep_only_value": f64["sweep_only_value"],
@@ -452,6 +493,8 @@ def main():
         out[name] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
                      "sweep_only_value": r["sweep_only_value"], "breakdown_ms": r["breakdown_ms"],
                      "sweep_tflops": r["sweep_flops_per_launch"] / (r["sweep_kernel_ms"] / 1e3) / 1e12,
+                     "slab_pass_ms": r["slab_kernel_ms"],
+                     "slab_pass_gbs": r["slab_bytes_per_launch"] / (r["slab_kernel_ms"] / 1e3) / 1e9,
                      "final_re": r["final_re"],
                      "re_gap_vs_fp64_pruned": abs(r["final_re"] - f64["final_re"]) / f64["final_re"]}
     if acc is not None:

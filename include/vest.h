@@ -204,6 +204,17 @@ int vest_set_kernel(vest_ctx *ctx, int32_t kernel);
  * waves, long rows, long-row chunks, max row length, rows, nnz. */
 int vest_layout_stats(vest_ctx *ctx, int32_t mode, int64_t *out);
 
+/* Instrumentation: kernel timing of the slab passes of the core sweep (the
+ * accumulating passes of Sec. 3.5's element updates grouped by slab, J^(N-2)
+ * launches per core sweep).  While enabled, each launch is bracketed by two
+ * HIP events on the context's stream (up to 1024 launches are recorded);
+ * vest_slab_time waits for the recorded launches, returns their summed
+ * duration in milliseconds and their count (host out), and clears the record.
+ * Enabling creates the events (the only allocation), disabling destroys them;
+ * VEST_EDEVICE if event creation fails. */
+int vest_slab_timing(vest_ctx *ctx, int32_t enable);
+int vest_slab_time(vest_ctx *ctx, double *ms, int64_t *launches);
+
 /* Release the context (not the workspace or any caller buffer).  Waits for
  * the context's queued work. */
 int vest_destroy(vest_ctx *ctx);

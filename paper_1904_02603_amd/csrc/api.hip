@@ -573,10 +573,63 @@ int vest_layout_stats(vest_ctx *c, int32_t mode, int64_t *out)
     return VEST_OK;
 }
 
+static void drop_slab_events(vest_ctx *c)
+{
+    for (int i = 0; i < 2 * c->slab_ev_cap; ++i) (void)hipEventDestroy(c->slab_ev[i]);
+    delete[] c->slab_ev;
+    c->slab_ev = nullptr;
+    c->slab_ev_cap = c->slab_ev_n = 0;
+}
+
+int vest_slab_timing(vest_ctx *c, int32_t enable)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (c->slab_ev) {
+        CALL_HIP(c, hipStreamSynchronize(c->stream), "timing sync");
+        drop_slab_events(c);
+    }
+    if (!enable) return VEST_OK;
+    const int cap = 1024;
+    c->slab_ev = new hipEvent_t[2 * cap];
+    for (int i = 0; i < 2 * cap; ++i) {
+        const hipError_t e = hipEventCreate(&c->slab_ev[i]);
+        if (e != hipSuccess) {
+            c->slab_ev_cap = i / 2;
+            if (i % 2) (void)hipEventDestroy(c->slab_ev[i - 1]);
+            drop_slab_events(c);
+            set_error("event creation failed: %s", hipGetErrorString(e));
+            return VEST_EDEVICE;
+        }
+    }
+    c->slab_ev_cap = cap;
+    c->slab_ev_n = 0;
+    return VEST_OK;
+}
+
+int vest_slab_time(vest_ctx *c, double *ms, int64_t *launches)
+{
+    int rc = live(c);
+    if (rc) return rc;
+    if (!ms || !launches) { set_error("null output"); return VEST_EINVAL; }
+    double total = 0.0;
+    for (int i = 0; i < c->slab_ev_n; ++i) {
+        CALL_HIP(c, hipEventSynchronize(c->slab_ev[2 * i + 1]), "timing sync");
+        float t = 0.0f;
+        CALL_HIP(c, hipEventElapsedTime(&t, c->slab_ev[2 * i], c->slab_ev[2 * i + 1]), "elapsed time");
+        total += t;
+    }
+    *ms = total;
+    *launches = c->slab_ev_n;
+    c->slab_ev_n = 0;
+    return VEST_OK;
+}
+
 int vest_destroy(vest_ctx *c)
 {
     if (!c) return VEST_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
+    if (c->slab_ev) drop_slab_events(c);
     delete c;
     if (e != hipSuccess) return device_error(nullptr, e, "destroy");
     return VEST_OK;

@@ -671,7 +671,10 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
         digits(s, a.lead);
         a.has_prev = s > 0 ? 1 : 0;
         if (s > 0) digits(s - 1, a.lprev);
+        const bool timed = c->slab_ev && c->slab_ev_n < c->slab_ev_cap;
+        if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n], st);
         if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, true>), dim3(blocks), dim3(256), 0, st, a);
+        if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n++ + 1], st);
         if (L.nlong > 0)
             hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
                                c->rowbuf, c->ldrb);

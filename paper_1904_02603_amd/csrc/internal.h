@@ -186,6 +186,8 @@ struct vest_ctx {
     double *key_core = nullptr;
     double *key_fac[VEST_MAX_ORDER] = {};
     bool dead = false;
+    hipEvent_t *slab_ev = nullptr;    // vest_slab_timing: start / end event pairs
+    int slab_ev_cap = 0, slab_ev_n = 0;
 };
 
 namespace vest {

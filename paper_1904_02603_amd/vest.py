@@ -23,7 +23,8 @@ KERNEL_AUTO, KERNEL_DENSE, KERNEL_GATHER = 0, 1, 2
 EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
            "vest_responsibility", "vest_prune", "vest_loss", "vest_normalize", "vest_count_nonzeros",
            "vest_export", "vest_test_error", "vest_value_keys", "vest_compact", "vest_set_kernel",
-           "vest_layout_stats", "vest_destroy", "vest_strerror", "vest_last_error",
+           "vest_layout_stats", "vest_slab_timing", "vest_slab_time", "vest_destroy", "vest_strerror",
+           "vest_last_error",
            "vest_server_create", "vest_server_submit", "vest_server_progress", "vest_server_status",
            "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -76,6 +77,8 @@ def load_library(path=LIB_PATH):
     lib.vest_test_error.argtypes = [vp, vp, vp, i64, vp]
     lib.vest_value_keys.argtypes = [vp, vp, vp]
     lib.vest_layout_stats.argtypes = [vp, i32, vp]
+    lib.vest_slab_timing.argtypes = [vp, i32]
+    lib.vest_slab_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
     lib.vest_destroy.argtypes = [vp]
     lib.vest_strerror.argtypes = [C.c_int]
     lib.vest_strerror.restype = C.c_char_p
@@ -268,6 +271,16 @@ class VestContext:
     def set_kernel(self, kernel):
         """Contraction kernel policy: KERNEL_AUTO, KERNEL_DENSE or KERNEL_GATHER."""
         _check(self.lib.vest_set_kernel(self.ctx, int(kernel)), "vest_set_kernel")
+
+    def slab_timing(self, enable=True):
+        """Record the duration of every slab pass of the core sweep (instrumentation)."""
+        _check(self.lib.vest_slab_timing(self.ctx, 1 if enable else 0), "vest_slab_timing")
+
+    def slab_time(self):
+        """(summed milliseconds, launches) of the slab passes recorded since the last call."""
+        ms, n = C.c_double(0.0), C.c_int64(0)
+        _check(self.lib.vest_slab_time(self.ctx, C.byref(ms), C.byref(n)), "vest_slab_time")
+        return ms.value, n.value
 
     def layout_stats(self, mode):
         out = (C.c_int64 * 8)()
