@@ -319,6 +319,46 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
+def scaling_study(iters=3, warmup=1):
+    """Time per Alg. 2 iteration (all factor sweeps + core sweep + loss) on the
+    synthetic tensors of the paper's scalability runs (Sec. 4, Fig. 4a-c),
+    ranks 3, FP64: (a) order 3..7 at dimensionality and |Omega| 10^3 (orders 8
+    to 10 have no kernel instance), (b) dimensionality 10^3..10^8 at order 3
+    with |Omega| equal to it, (c) |Omega| 10^3..10^7 at order 3, dimensionality
+    10^3."""
+    import torch
+    from paper_1904_02603_amd import synth, vest
+    runs = {"order": [(N, 10 ** 3, 10 ** 3) for N in range(3, 8)],
+            "dimensionality": [(3, 10 ** e, 10 ** e) for e in range(3, 9)],
+            "entries": [(3, 10 ** 3, 10 ** e) for e in range(3, 8)]}
+    out = {}
+    for name, cases in runs.items():
+        out[name] = []
+        for N, I, nnz in cases:
+            t0 = time.perf_counter()
+            p = synth.scaling_problem(N, I, nnz)
+            gen = time.perf_counter() - t0
+            ctx = vest.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"])
+            del p
+            for _ in range(warmup):
+                ctx.iteration()
+                ctx.loss()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(iters):
+                ctx.iteration()
+                ctx.loss()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / iters
+            out[name].append({"order": N, "dim": I, "nnz": nnz, "ms_per_iteration": ms,
+                              "entry_updates_per_s": N * nnz / (ms / 1e3)})
+            log("  %s: N %d, I %d, nnz %d: %.3f ms per iteration (inputs %.1f s)" % (name, N, I, nnz, ms, gen))
+            ctx.close()
+            del ctx
+            torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(kernel):
     """Calibrated HBM bytes per launch of a kernel from its committed counter
     summary, or None if the kernel's sources changed since."""
@@ -385,6 +425,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counters)")
+    ap.add_argument("--scaling", action="store_true",
+                    help="run only the scalability study (order, dimensionality, entries) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -402,6 +444,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.scaling:
+        log("scalability study ...")
+        print(json.dumps({"study": "scalability (Sec. 4, Fig. 4a-c)", "ranks": 3, "dtype": "f64", "data": "synthetic",
+                          "timing": "wall clock per Alg. 2 iteration (factor sweeps + core sweep + loss), 3 after 1",
+                          "results": scaling_study()}))
+        return
     t0 = time.perf_counter()
     log("generating workload %s ..." % args.workload)
     p = synth.workload(args.workload, nnz=args.nnz)

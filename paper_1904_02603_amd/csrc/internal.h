@@ -31,7 +31,7 @@
 
 // (order, uniform rank) pairs with compiled kernel instances.
 #define VEST_SHAPES(X) X(2, 2) X(2, 3) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 8) X(3, 10) \
-    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8)
+    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(5, 3) X(6, 3) X(7, 3)
 
 namespace vest {
 

@@ -227,6 +227,40 @@ def serving_init(job, dims):
     return initial_state(dims, job["ranks"], np.random.Generator(np.random.PCG64(list(job["init_seed"]))))
 
 
+def scaling_problem(order, dim, nnz, seed=SEED_BASE + 7, rank=3):
+    """Synthetic tensor of the scalability runs (Sec. 4, Fig. 4a-c): every mode
+    of size `dim`, ranks `rank`, `nnz` distinct entries drawn uniformly, values
+    U[0, 1), initial state U[0, 1).  Distinctness: by flat index when the index
+    space fits in 62 bits, otherwise by giving every entry its own mode-0 index
+    (a seeded permutation; needs nnz <= dim)."""
+    rng = np.random.default_rng(seed)
+    N = int(order)
+    if N * math.log2(max(dim, 2)) <= 62:
+        total = dim ** N
+        if nnz > total:
+            raise ValueError("more entries than cells")
+        flat = np.unique(rng.integers(0, total, size=nnz, dtype=np.int64))
+        while flat.size < nnz:
+            more = rng.integers(0, total, size=nnz - flat.size, dtype=np.int64)
+            flat = np.unique(np.concatenate([flat, more]))
+        flat = rng.permutation(flat)
+        idx = np.empty((nnz, N), dtype=np.int32)
+        for n in range(N - 1, -1, -1):
+            idx[:, n] = flat % dim
+            flat //= dim
+    else:
+        if nnz > dim:
+            raise ValueError("distinct entries by mode-0 index need nnz <= dim")
+        idx = np.empty((nnz, N), dtype=np.int32)
+        idx[:, 0] = rng.permutation(dim)[:nnz]
+        for n in range(1, N):
+            idx[:, n] = rng.integers(0, dim, size=nnz, dtype=np.int32)
+    val = rng.random(nnz)
+    factors = [rng.random((dim, rank)) for _ in range(N)]
+    core = rng.random((rank,) * N)
+    return {"idx": idx, "val": val, "factors": factors, "core": core, "reg": 0, "lam": 0.01}
+
+
 def workload(name, nnz=None, dims=None):
     """Build a named workload (optionally with a smaller nnz / dims)."""
     w = dict(WORKLOADS[name])

@@ -1,0 +1,70 @@
+"""GPU parity at orders 5 to 7 (ranks 3), the shapes of the order-scaling
+workload (the paper's runtime against tensor order, Fig. 4a).
+
+Same bar as the order-3 / order-4 parity: FP64 factors, core, loss and keys
+within 1e-10 of the oracle, prune masks identical; the FP32 form's loss within
+1e-6 after an iteration.  At order 7 the core has 2187 elements, so the core
+sweep runs 243 slab passes and the core keys several batches.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.oracle import REG_L1, REG_LF
+from test_gpu_parity import V, assert_state, keys_close, make, pair, say
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = [
+    ((9, 8, 7, 6, 8), 1500),
+    ((7, 6, 6, 5, 6, 7), 1500),
+    ((6, 5, 5, 4, 4, 5, 6), 1200),
+]
+IDS = ["N5J3", "N6J3", "N7J3"]
+
+
+@pytest.mark.parametrize("reg", [REG_LF, REG_L1], ids=["LF", "L1"])
+@pytest.mark.parametrize("case", ORDERS, ids=IDS)
+def test_iteration_keys_and_prune_match_oracle(case, reg):
+    dims, nnz = case
+    ranks = (3,) * len(dims)
+    say("case", dims, nnz, reg)
+    p = make(dims, ranks, nnz, 91)
+    rng = np.random.default_rng(92)
+    fmask = [(rng.random((d, 3)) < 0.05).astype(np.uint8) for d in dims]
+    cmask = (rng.random(ranks) < 0.1).astype(np.uint8)
+    g, o = pair(p, reg, 0.05 if reg == REG_LF else 0.3, fmask=fmask, cmask=cmask)
+    g.iteration()
+    o.iteration()
+    assert_state(g, o, what="iteration")
+    gl, ol = g.loss(), o.loss()
+    for k in ["sse", "reg", "loss", "re"]:
+        assert abs(gl[k] - ol[k]) <= 1e-10 * abs(ol[k]) + 1e-300, (k, gl[k], ol[k])
+    gck, gfk = g.responsibility()
+    ock, ofk = o.responsibility()
+    keys_close(gck, ock, "core keys")
+    for n in range(len(dims)):
+        keys_close(gfk[n], ofk[n], "factor keys %d" % n)
+    ck = max(1, int(0.2 * (cmask == 0).sum()))
+    fk = [max(1, int(0.1 * (m == 0).sum())) for m in fmask]
+    g.prune(ck, fk)
+    o.prune(ock, ofk, ck, fk)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cmask.cpu().numpy().astype(bool), o.cmask.astype(bool)), "core mask"
+    for n, m in enumerate(g.factor_masks_bool()):
+        assert np.array_equal(m.cpu().numpy(), o.fmask[n].astype(bool)), "factor mask %d" % n
+    g.iteration()
+    o.iteration()
+    assert_state(g, o, what="iteration after prune")
+
+
+def test_order6_fp32_form_tracks_oracle():
+    dims, nnz = ORDERS[1]
+    p = make(dims, (3,) * len(dims), nnz, 93)
+    g, o = pair(p, REG_LF, 0.05, precision=V().FP32)
+    g.iteration()
+    o.iteration()
+    gl, ol = g.loss(), o.loss()
+    gap = abs(gl["loss"] - ol["loss"]) / ol["loss"]
+    say("order-6 FP32 loss gap %.3e" % gap)
+    assert gap <= 1e-6
