@@ -155,8 +155,8 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     c->partials = (double *)take(p.chunk_bound * na * 8);
     c->red = (double *)take((16 * kLossBlocks + 64) * 8);
     c->flags = (int32_t *)take(64);
-    c->pk_in = (uint64_t *)take(p.max_tensor * 8);
-    c->pk_out = (uint64_t *)take(p.max_tensor * 8);
+    c->sel_hist = (uint32_t *)take((size_t)(VEST_MAX_ORDER + 1) * 4096 * 4);
+    c->sel_state = (char *)take((size_t)(VEST_MAX_ORDER + 1) * 24);
     c->pv_in = (uint32_t *)take(p.max_tensor * 4);
     c->pv_out = (uint32_t *)take(p.max_tensor * 4);
     c->sort_tmp = take(p.sort_tmp);
@@ -410,14 +410,13 @@ int vest_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
             set_error("factor count %lld of mode %d out of range", (long long)factor_k[n], n);
             return VEST_EINVAL;
         }
+    CALL_HIP(c, launch_prune(c, core_k, factor_k), "prune");
     if (core_k > 0) {
-        CALL_HIP(c, launch_prune(c, -1, core_k), "prune core");
         c->marked_core += core_k;
         c->core_version++;
     }
     for (int n = 0; n < c->N; ++n)
         if (factor_k[n] > 0) {
-            CALL_HIP(c, launch_prune(c, n, factor_k[n]), "prune factor");
             c->marked_fac[n] += factor_k[n];
             c->ag_valid[n] = false;
             c->ms_valid = false;

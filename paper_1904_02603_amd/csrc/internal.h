@@ -161,8 +161,9 @@ struct vest_ctx {
     double *partials = nullptr;       // long-row chunk partials
     double *red = nullptr;            // reduction scratch [4 * kLossBlocks + 16]
     int32_t *flags = nullptr;         // device error flags [16]
-    uint64_t *pk_in = nullptr, *pk_out = nullptr;  // prune keys
-    uint32_t *pv_in = nullptr, *pv_out = nullptr;  // prune positions
+    uint32_t *pv_in = nullptr, *pv_out = nullptr;  // nonzero flags / positions (export)
+    uint32_t *sel_hist = nullptr;     // prune selection: [N + 1][4096] digit counts
+    char *sel_state = nullptr;        // prune selection: chosen digits and counts per tensor
     void *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
     double *host_red = nullptr;       // pinned host mirror of small results
@@ -210,7 +211,7 @@ hipError_t launch_core_keys(vest_ctx *c, double *core_key);
 hipError_t launch_permute_core(vest_ctx *c, int mode);
 hipError_t launch_gather_copy(vest_ctx *c, int mode);
 hipError_t launch_loss(vest_ctx *c, double *dev_out3);          // sse, reg (device)
-hipError_t launch_prune(vest_ctx *c, int tensor, int64_t k);     // tensor -1 = core
+hipError_t launch_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k);  // all tensors at once
 hipError_t launch_sumsq(hipStream_t s, const double *v, int64_t n, double *partial, double *out);
 hipError_t launch_mask_init(vest_ctx *c, int64_t *counts_dev);
 hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, char *scratch,

@@ -210,58 +210,162 @@ hipError_t launch_mask_init(vest_ctx *c, int64_t *counts_dev)
 
 // ------------------------------------------------------------- pruning
 // FP64 key -> unsigned integer with the same order (-0 and +0 equal).
-__global__ void __launch_bounds__(256) k_keybits(const double *__restrict__ key, int64_t n,
-                                                 uint64_t *__restrict__ kout, uint32_t *__restrict__ pout)
+// ------------------------------------------------------------------ prune
+// The k unmarked elements with the smallest (key, flat index) of every tensor
+// that prunes this step, all tensors at once, by radix selection over the
+// 96-bit composite (order-preserving 64-bit image of the FP64 key, 32-bit flat
+// index): eight rounds of 12-bit digits, most significant first.  A round
+// counts the digit of every element whose higher digits equal the ones chosen
+// so far (block-local LDS histograms added into one histogram per tensor);
+// then one block per tensor takes the digit at which the running count reaches
+// the k still to place.  The composites of a tensor are distinct, so after the
+// last round exactly k of its elements lie at or below the chosen composite;
+// they are zeroed and marked.  Marked elements carry +inf keys and never
+// qualify (k never exceeds the unmarked count).
+constexpr int kSelBits = 12, kSelBins = 1 << kSelBits, kSelRounds = 96 / kSelBits, kSelPerBlock = 4096;
+typedef unsigned __int128 u128;
+
+struct SelSeg {
+    const double *key;
+    double *val;        // core or factor values
+    uint32_t *fmask;    // factor marking words (null for the core)
+    uint8_t *cmask;     // core marks (null for a factor)
+    int64_t n, k;
+    int64_t block0;     // first block of this tensor in a pass
+    int32_t J;
+};
+struct SelArgs {
+    SelSeg seg[VEST_MAX_ORDER + 1];
+    int32_t nseg;
+    uint32_t *hist;     // [nseg][kSelBins]
+    u128 *pref;         // [nseg] digits chosen so far
+    int64_t *krem;      // [nseg] elements still to place
+};
+
+__device__ __forceinline__ u128 sel_composite(double k, int64_t i)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    double k = key[q];
-    if (k == 0.0) k = 0.0;
+    if (k == 0.0) k = 0.0;   // -0 and +0 are one key
     uint64_t u = (uint64_t)__double_as_longlong(k);
     u = (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-    kout[q] = u;
-    pout[q] = (uint32_t)q;
+    return ((u128)u << 32) | (uint32_t)i;
 }
 
-__global__ void __launch_bounds__(256) k_mark_core(const uint32_t *__restrict__ pos, int64_t k, double *__restrict__ core,
-                                                   uint8_t *__restrict__ mask)
+__device__ __forceinline__ int sel_segment(const SelArgs &a, int64_t b)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= k) return;
-    const uint32_t q = pos[t];
-    core[q] = 0.0;
-    mask[q] = 1;
+    int s = 0;
+    while (s + 1 < a.nseg && a.seg[s + 1].block0 <= b) ++s;
+    return s;
 }
 
-__global__ void __launch_bounds__(256) k_mark_factor(const uint32_t *__restrict__ pos, int64_t k, int J,
-                                                     double *__restrict__ A, uint32_t *__restrict__ mask)
+__global__ void __launch_bounds__(256) k_sel_init(SelArgs a)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= k) return;
-    const uint32_t q = pos[t];
-    A[q] = 0.0;
-    atomicOr(&mask[q / J], 1u << (q % J));
+    const int s = blockIdx.x;
+    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) a.hist[(int64_t)s * kSelBins + i] = 0u;
+    if (threadIdx.x == 0) {
+        a.pref[s] = 0;
+        a.krem[s] = a.seg[s].k;
+    }
 }
 
-// Zero and mark the k unmarked elements with the smallest (key, flat index):
-// marked elements carry +inf keys, and the LSD radix sort is stable over the
-// index-ordered input, so equal keys stay in index order.
-hipError_t launch_prune(vest_ctx *c, int tensor, int64_t k)
+__global__ void __launch_bounds__(256) k_sel_hist(SelArgs a, int round)
+{
+    __shared__ uint32_t h[kSelBins];
+    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    const int s = sel_segment(a, blockIdx.x);
+    const SelSeg &g = a.seg[s];
+    const int64_t lo = ((int64_t)blockIdx.x - g.block0) * kSelPerBlock;
+    const int64_t hi = lo + kSelPerBlock < g.n ? lo + kSelPerBlock : g.n;
+    const int top = 96 - kSelBits * round;   // digits at and above `top` are chosen
+    const u128 p = a.pref[s];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const u128 c = sel_composite(g.key[i], i);
+        if ((c >> top) == p) atomicAdd(&h[(uint32_t)(c >> (top - kSelBits)) & (kSelBins - 1)], 1u);
+    }
+    __syncthreads();
+    uint32_t *gh = a.hist + (int64_t)s * kSelBins;
+    for (int i = threadIdx.x; i < kSelBins; i += blockDim.x)
+        if (h[i]) atomicAdd(&gh[i], h[i]);
+}
+
+// One block of 1024 threads per tensor, four bins per thread.
+__global__ void __launch_bounds__(1024) k_sel_pick(SelArgs a)
+{
+    __shared__ uint32_t part[1024];
+    const int s = blockIdx.x, t = threadIdx.x;
+    uint32_t *gh = a.hist + (int64_t)s * kSelBins;
+    uint32_t c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = gh[4 * t + q];
+    part[t] = c[0] + c[1] + c[2] + c[3];
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {   // inclusive scan of the thread sums
+        const uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const int64_t krem = a.krem[s];
+    int64_t run = t > 0 ? part[t - 1] : 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (run < krem && run + c[q] >= krem) {
+            a.pref[s] = (a.pref[s] << kSelBits) | (u128)(4 * t + q);
+            a.krem[s] = krem - run;
+        }
+        run += c[q];
+        gh[4 * t + q] = 0u;   // clean for the next round
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sel_mark(SelArgs a)
+{
+    const int s = sel_segment(a, blockIdx.x);
+    const SelSeg &g = a.seg[s];
+    const int64_t lo = ((int64_t)blockIdx.x - g.block0) * kSelPerBlock;
+    const int64_t hi = lo + kSelPerBlock < g.n ? lo + kSelPerBlock : g.n;
+    const u128 thr = a.pref[s];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        if (sel_composite(g.key[i], i) > thr) continue;
+        g.val[i] = 0.0;
+        if (g.fmask) atomicOr(&g.fmask[i / g.J], 1u << (i % g.J));
+        else g.cmask[i] = 1;
+    }
+}
+
+// core_k for the core, factor_k[n] for mode n (0 = leave that tensor alone).
+hipError_t launch_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
 {
     hipStream_t st = c->stream;
-    const int64_t n = tensor < 0 ? c->G : c->d.dims[tensor] * c->J;
-    const double *key = tensor < 0 ? c->key_core : c->key_fac[tensor];
-    hipLaunchKernelGGL(k_keybits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, n, c->pk_in, c->pv_in);
-    size_t bytes = c->sort_tmp_bytes;
-    hipError_t err = hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, bytes, c->pk_in, c->pk_out, c->pv_in, c->pv_out,
-                                                        (int)n, 0, 64, st);
-    if (err != hipSuccess) return err;
-    const unsigned blocks = (unsigned)((k + 255) / 256);
-    if (tensor < 0)
-        hipLaunchKernelGGL(k_mark_core, dim3(blocks), dim3(256), 0, st, c->pv_out, k, c->core, c->cmask);
-    else
-        hipLaunchKernelGGL(k_mark_factor, dim3(blocks), dim3(256), 0, st, c->pv_out, k, c->J, c->A[tensor],
-                           c->fmask[tensor]);
+    SelArgs a{};
+    int64_t blocks = 0;
+    auto add = [&](const double *key, double *val, uint32_t *fm, uint8_t *cm, int64_t n, int64_t k) {
+        if (k <= 0) return;
+        SelSeg &g = a.seg[a.nseg++];
+        g.key = key;
+        g.val = val;
+        g.fmask = fm;
+        g.cmask = cm;
+        g.n = n;
+        g.k = k;
+        g.J = c->J;
+        g.block0 = blocks;
+        blocks += (n + kSelPerBlock - 1) / kSelPerBlock;
+    };
+    add(c->key_core, c->core, nullptr, c->cmask, c->G, core_k);
+    for (int n = 0; n < c->N; ++n)
+        add(c->key_fac[n], c->A[n], c->fmask[n], nullptr, c->d.dims[n] * c->J, factor_k[n]);
+    if (a.nseg == 0) return hipSuccess;
+    a.hist = c->sel_hist;
+    a.pref = reinterpret_cast<u128 *>(c->sel_state);
+    a.krem = reinterpret_cast<int64_t *>(c->sel_state + 16 * (VEST_MAX_ORDER + 1));
+    hipLaunchKernelGGL(k_sel_init, dim3(a.nseg), dim3(256), 0, st, a);
+    for (int r = 0; r < kSelRounds; ++r) {
+        hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)blocks), dim3(256), 0, st, a, r);
+        hipLaunchKernelGGL(k_sel_pick, dim3(a.nseg), dim3(1024), 0, st, a);
+    }
+    hipLaunchKernelGGL(k_sel_mark, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
