@@ -38,6 +38,7 @@ struct SlabArgs {
     const int32_t *row_order;
     const int32_t *oidx[N - 1];   // core layout: modes 0..N-2
     const T *colA[NL];            // column-major copies of modes 0..N-3
+    const T *rowA[NL];            // gather copies of modes 0..N-3 (row stride gather_ld)
     int64_t dimA[NL];
     int32_t lead[NL];             // leading core indices of this slab
     int32_t lprev[NL];            // ... of the previous slab
@@ -181,13 +182,20 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 
 // Core responsibility statistics of SB consecutive slabs in one pass:
 // per row r and slab b,  R_b[t] = sum e p_b a^(N-1)_t  and, when WITH_D,
-// D_b[t] = sum (p_b a^(N-1)_t)^2.  The residual is not modified.  Loads as in
-// k_slab.
+// D_b[t] = sum (p_b a^(N-1)_t)^2.  The residual is not modified.  Streamed
+// loads as in k_slab.  The leading factor values p_b of the SB slabs come
+// either from SB column gathers (column copies of the leading modes) or, in
+// the ROWP form, from one gathered row per leading mode (one cache line) and
+// an exact arithmetic pick of the slab's digit.
 template <int N, int J, typename T, int SB, bool WITH_D>
 __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
 {
     constexpr int PER = WITH_D ? 2 * J : J;
     constexpr int NA = PER * SB;
+    // FP64 at order 3: one leading row per entry (see above); elsewhere (FP32 or
+    // more leading modes) the rows and picks cost more registers than the
+    // column gathers save, and the leading values come from the column copies
+    constexpr bool ROWP = N == 3 && sizeof(T) == 8;
     constexpr int U = slab_u<T>();
     constexpr int NL = SlabArgs<N, J, T>::NL;
     constexpr int NI = N > 2 ? N - 2 : 1;
@@ -214,7 +222,7 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
     for (int k0 = 0; k0 < wi.K; k0 += U) {
         int64_t sl[U];
         int32_t ni[U][NI];
-        T mv[U][J], ev[U];
+        T mv[U][J], ev[U], lr[U][NI][J];
         load_idx(k0 + U, ni);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -223,6 +231,12 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
             ev[q] = a.e[sl[q]];
 #pragma unroll
             for (int t = 0; t < J; ++t) mv[q][t] = a.ms[ms_index<J>(sl[q], t)];
+            if constexpr (ROWP) {
+#pragma unroll
+                for (int m = 0; m < N - 2; ++m)
+                    load_grow<J, T>(a.rowA[m] + (int64_t)(ii[q][m] > 0 ? ii[q][m] : 0) * gather_ld(J, sizeof(T)),
+                                    lr[q][m]);
+            }
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -237,8 +251,12 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
                     T p = T(1);
 #pragma unroll
                     for (int m = 0; m < N - 2; ++m) {
-                        const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
-                        p *= a.colA[m][(int64_t)a.blead[b * NL + m] * a.dimA[m] + i];
+                        if constexpr (ROWP) {
+                            p *= pick<J, T>(lr[q][m], a.blead[b * NL + m]);
+                        } else {
+                            const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
+                            p *= a.colA[m][(int64_t)a.blead[b * NL + m] * a.dimA[m] + i];
+                        }
                     }
                     const T ep = evq * p;
 #pragma unroll
@@ -642,6 +660,7 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
         a.dimA[m] = I;
     }
     a.ms = reinterpret_cast<const T *>(c->ms);
+    for (int m = 0; m < N - 2; ++m) a.rowA[m] = reinterpret_cast<const T *>(c->Ag[m]);
     a.Alast = reinterpret_cast<const T *>(c->Ag[last]);
     a.e = reinterpret_cast<T *>(c->e);
     a.dprev = c->dprev;

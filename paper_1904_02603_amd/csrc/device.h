@@ -248,6 +248,18 @@ __device__ __forceinline__ void load_row(const T *__restrict__ p, T (&r)[J])
     }
 }
 
+// r[b] for a per-lane (or runtime) b, as a sum with exactly one nonzero term (a select
+// chain would be folded back into a dynamically indexed array, which lives
+// in scratch memory).
+template <int J, typename T>
+__device__ __forceinline__ T pick(const T (&r)[J], int b)
+{
+    T v = r[0] * (b == 0 ? T(1) : T(0));
+#pragma unroll
+    for (int t = 1; t < J; ++t) v = vfma(r[t], b == t ? T(1) : T(0), v);
+    return v;
+}
+
 // Load a row of a gather copy (16-byte aligned start): 16-byte loads, then
 // the remainder in 8- and 4-byte pieces.
 template <int J, typename T>

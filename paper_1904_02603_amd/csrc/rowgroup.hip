@@ -85,18 +85,6 @@ __device__ __forceinline__ void row_epilogue(const RowArgs<N, J, T> &a, int row,
 // combinations of nonzero values of its entry's other-mode rows whose core
 // column is nonzero, so the work per entry is proportional to the number of
 // surviving terms instead of J^N.
-// r[b] for a per-lane b, as a sum with exactly one nonzero term (a select
-// chain would be folded back into a dynamically indexed array, which lives
-// in scratch memory).
-template <int J, typename T>
-__device__ __forceinline__ T pick(const T (&r)[J], int b)
-{
-    T v = r[0] * (b == 0 ? T(1) : T(0));
-#pragma unroll
-    for (int t = 1; t < J; ++t) v = vfma(r[t], b == t ? T(1) : T(0), v);
-    return v;
-}
-
 template <int L, int N, int J, typename T>
 __device__ __forceinline__ void gather_level(const T *__restrict__ Gt, const uint32_t *__restrict__ Gnz,
                                              const T (&r)[N - 1][J], const uint32_t (&m)[N - 1], T w, int o,
