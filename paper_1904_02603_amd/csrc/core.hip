@@ -192,11 +192,11 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
 {
     constexpr int PER = WITH_D ? 2 * J : J;
     constexpr int NA = PER * SB;
-    // FP64 at order 3: one leading row per entry (see above); elsewhere (FP32 or
-    // more leading modes) the rows and picks cost more registers than the
-    // column gathers save, and the leading values come from the column copies
-    constexpr bool ROWP = N == 3 && sizeof(T) == 8;
-    constexpr int U = slab_u<T>();
+    // Order 3: one leading row per entry (see above), FP32 one entry per batch
+    // to keep the row and the picks in registers; with more leading modes the
+    // rows and picks cost more registers than the column gathers save
+    constexpr bool ROWP = N == 3;
+    constexpr int U = (ROWP && sizeof(T) == 4) ? 1 : slab_u<T>();
     constexpr int NL = SlabArgs<N, J, T>::NL;
     constexpr int NI = N > 2 ? N - 2 : 1;
     const int lane = threadIdx.x & (kWave - 1);
