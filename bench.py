@@ -43,14 +43,13 @@ def sweep_flops_per_entry(N, J):
 
 
 def slab_bytes_per_launch(N, J, nnz, dims, ts):
-    """Algorithmic HBM bytes of one slab pass of the core sweep, averaged over
-    the J^(N-2) passes of a sweep: per entry the residual (read; written by
-    every pass but the first), the slot copy of the mode N-2 row (J values) and
-    the N-2 leading indices; once per pass the per-row statistics of the last
-    mode (J + J(J+1)/2 FP64 values), that mode's factor rows and the two
-    leading-factor columns."""
-    nslab = J ** (N - 2)
-    per_entry = ts + J * ts + 4 * (N - 2) + ts * (nslab - 1) / nslab
+    """Algorithmic HBM bytes of one timed slab pass of the core sweep (passes 2
+    to J^(N-2); the first slab's statistics come from the residual pass): per
+    entry the residual read and written, the slot copy of the mode N-2 row (J
+    values) and the N-2 leading indices; once per pass the per-row statistics
+    of the last mode (J + J(J+1)/2 FP64 values), that mode's factor rows and
+    the two leading-factor columns."""
+    per_entry = 2 * ts + J * ts + 4 * (N - 2)
     rows = dims[N - 1]
     once = rows * (J + J * (J + 1) // 2) * 8 + rows * J * ts + sum(2 * d * ts for d in dims[:N - 2])
     return nnz * per_entry + once

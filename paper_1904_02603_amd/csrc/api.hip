@@ -371,8 +371,17 @@ int vest_sweep_core(vest_ctx *c)
 {
     int rc = live(c);
     if (rc) return rc;
-    if ((rc = ensure_residual(c))) return rc;
-    CALL_HIP(c, launch_core_sweep(c), "core sweep");
+    // when the residual has to be formed anyway, its pass also accumulates
+    // the first slab's statistics (dense form)
+    bool fused = false;
+    if (!(c->e_valid && c->ms_valid)) {
+        if ((rc = ensure_ag(c)) || (rc = ensure_gp(c, c->N - 1))) return rc;
+        fused = resid_fuses_slab0(c);
+        CALL_HIP(c, launch_rowgroup(c, c->N - 1, fused ? OP_RESID_S0 : OP_RESID), "residual");
+        c->e_valid = true;
+        c->ms_valid = true;
+    }
+    CALL_HIP(c, launch_core_sweep(c, fused), "core sweep");
     c->core_version++;
     c->e_valid = true;
     c->hdiag_valid = true;

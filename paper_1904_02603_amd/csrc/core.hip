@@ -639,7 +639,7 @@ static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out)
 }
 
 template <int N, int J, typename T>
-static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
+static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab0_done)
 {
     const int last = N - 1;
     const ModeLayout &L = c->lay[last];
@@ -690,10 +690,13 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
         digits(s, a.lead);
         a.has_prev = s > 0 ? 1 : 0;
         if (s > 0) digits(s - 1, a.lprev);
-        const bool timed = c->slab_ev && c->slab_ev_n < c->slab_ev_cap;
-        if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n], st);
-        if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, true>), dim3(blocks), dim3(256), 0, st, a);
-        if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n++ + 1], st);
+        // the first slab's statistics may already come from the residual pass (OP_RESID_S0)
+        if (!(s == 0 && slab0_done)) {
+            const bool timed = c->slab_ev && c->slab_ev_n < c->slab_ev_cap;
+            if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n], st);
+            if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, true>), dim3(blocks), dim3(256), 0, st, a);
+            if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n++ + 1], st);
+        }
         if (L.nlong > 0)
             hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
                                c->rowbuf, c->ldrb);
@@ -712,19 +715,19 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out)
     return hipGetLastError();
 }
 
-static hipError_t core_pass(vest_ctx *c, bool keys, double *key_out)
+static hipError_t core_pass(vest_ctx *c, bool keys, double *key_out, bool slab0_done)
 {
 #define VEST_CASE(NN, JJ)                                                                \
     if (c->N == NN && c->J == JJ)                                                        \
-        return c->f32 ? core_pass_t<NN, JJ, float>(c, keys, key_out) \
-                                           : core_pass_t<NN, JJ, double>(c, keys, key_out);
+        return c->f32 ? core_pass_t<NN, JJ, float>(c, keys, key_out, slab0_done) \
+                                           : core_pass_t<NN, JJ, double>(c, keys, key_out, slab0_done);
     VEST_SHAPES(VEST_CASE)
 #undef VEST_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_core_sweep(vest_ctx *c) { return core_pass(c, false, nullptr); }
-hipError_t launch_core_keys(vest_ctx *c, double *core_key) { return core_pass(c, true, core_key); }
+hipError_t launch_core_sweep(vest_ctx *c, bool slab0_done) { return core_pass(c, false, nullptr, slab0_done); }
+hipError_t launch_core_keys(vest_ctx *c, double *core_key) { return core_pass(c, true, core_key, false); }
 
 bool shape_supported(int N, int J)
 {

@@ -79,7 +79,9 @@ struct ModeLayout {
 };
 
 // Operations of the row-group kernel.
-enum RowOp { OP_SWEEP = 0, OP_KEYS = 1, OP_RESID = 2, OP_SLAB = 3, OP_APPLY = 4 };
+// OP_RESID_S0: the residual pass of the core layout that also accumulates the
+// first slab's statistics (the first slab pass of the core sweep, fused)
+enum RowOp { OP_SWEEP = 0, OP_KEYS = 1, OP_RESID = 2, OP_RESID_S0 = 3 };
 
 // Number of per-row accumulators of an operation.
 __host__ __device__ constexpr int nacc_vc(int J) { return J * (J + 1) / 2 + J; }
@@ -197,8 +199,9 @@ namespace vest {
 // (defined in the .hip files; return hipSuccess or the first HIP error)
 bool shape_supported(int N, int J);
 
-hipError_t launch_rowgroup(vest_ctx *c, int mode, int op);       // OP_SWEEP / OP_KEYS / OP_RESID
-hipError_t launch_core_sweep(vest_ctx *c);
+hipError_t launch_rowgroup(vest_ctx *c, int mode, int op);       // OP_SWEEP / OP_KEYS / OP_RESID / OP_RESID_S0
+bool resid_fuses_slab0(const vest_ctx *c);                       // OP_RESID_S0 applies (dense form)
+hipError_t launch_core_sweep(vest_ctx *c, bool slab0_done);
 hipError_t launch_normalize(vest_ctx *c);
 hipError_t launch_count_nonzeros(vest_ctx *c, int64_t *counts);  // synchronises
 hipError_t launch_export(vest_ctx *c, int64_t *const *fi, double *const *fv, int64_t *ci, double *cv);

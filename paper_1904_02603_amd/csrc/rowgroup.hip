@@ -41,10 +41,12 @@ struct RowArgs {
     T *e;                     // OP_RESID: out
     T *ms;                    // OP_RESID: out, mode N-2 factor row of every slot (see ms_index)
     double *keys;             // OP_KEYS: out [I_n * J]
+    double *rowbuf;           // OP_RESID_S0: per-row statistics of the first slab
+    int32_t ldrb;
 };
 
 template <int J, int OP>
-__host__ __device__ constexpr int row_nacc() { return OP == OP_KEYS ? 2 * J : nacc_vc(J); }
+__host__ __device__ constexpr int row_nacc() { return OP == OP_KEYS ? 2 * J : nacc_vc(J); }   // (OP_RESID: unused)
 
 // FP64 epilogue of one row given its summed statistics s.
 template <int N, int J, typename T, int OP, typename S>
@@ -271,7 +273,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
     const int row = has_row ? a.row_order[wi.first + grp] : 0;
 
     T own[J];
-    if constexpr (OP == OP_RESID || OP == OP_KEYS) {
+    if constexpr (OP != OP_SWEEP) {
         if (has_row) load_grow<J, T>(a.Ag + (int64_t)row * gather_ld(J, sizeof(T)), own);
         else
 #pragma unroll
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
 
-    if constexpr (!GA && OP != OP_SWEEP) {
+    if constexpr (!GA && (OP == OP_KEYS || OP == OP_RESID)) {
         pair_steps<N, J, T, OP>(a, Gb, wi, lane, own, s);
     } else {
     // Software pipeline: the indices and value of step k + 1 (gather form:
@@ -321,7 +323,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
         load_step(k + AHEAD, ni, nx);
         if constexpr (GA) load_marks(pi, nm);
         if (ci[0] < 0) {
-            if constexpr (OP == OP_RESID) {
+            if constexpr (OP == OP_RESID || OP == OP_RESID_S0) {
                 a.e[sl] = T(0);
 #pragma unroll
                 for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
@@ -362,9 +364,26 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
                         s[J + t] = vfma(d[t], d[t], s[J + t]);
                     }
                 } else {
-                    a.e[sl] = x - b;
+                    const T ev = x - b;
+                    a.e[sl] = ev;
 #pragma unroll
                     for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
+                    if constexpr (OP == OP_RESID_S0) {
+                        // first slab (leading digits 0): w_t = prod_m a^(m)_{i_m 0} a^(N-2)_{i t},
+                        // accumulated as the slab pass does
+                        T p = T(1);
+#pragma unroll
+                        for (int m = 0; m < N - 2; ++m) p *= r[m][0];
+                        T w[J];
+#pragma unroll
+                        for (int t = 0; t < J; ++t) w[t] = p * r[N - 2][t];
+#pragma unroll
+                        for (int t = 0; t < J; ++t) {
+                            s[t] = vfma(ev, w[t], s[t]);
+#pragma unroll
+                            for (int v = t; v < J; ++v) s[J + sym<J>(t, v)] = vfma(w[t], w[v], s[J + sym<J>(t, v)]);
+                        }
+                    }
                 }
             }
         }
@@ -386,6 +405,15 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
     }
     if constexpr (OP == OP_RESID) {
         return;
+    } else if constexpr (OP == OP_RESID_S0) {
+        group_reduce<NA, T>(s, wi.glog);
+        if (wi.chunk >= 0) {
+            store_partial<NA, T>(a.partials, wi.chunk, s, lane);
+        } else if (has_row && (lane & ((1 << wi.glog) - 1)) == 0) {
+            double *dst = a.rowbuf + (int64_t)row * a.ldrb;
+#pragma unroll
+            for (int v = 0; v < NA; ++v) dst[v] = (double)s[v];
+        }
     } else {
         group_reduce<NA, T>(s, wi.glog);
         if (wi.chunk >= 0) {
@@ -646,10 +674,13 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     a.e = reinterpret_cast<T *>(c->e);
     a.ms = reinterpret_cast<T *>(c->ms);
     a.keys = c->key_fac[mode];
+    a.rowbuf = c->rowbuf;
+    a.ldrb = c->ldrb;
     const T *Gp = reinterpret_cast<const T *>(c->Gp[mode]);
     const int blocks = (L.nwaves + 3) / 4;
     const bool ga = use_gather(c, mode, (N == 3 && J <= 16 && std::is_same<T, float>::value && op == OP_SWEEP));
     const size_t lds = ga ? gather_lds_bytes<N, J, T>() : 0;
+    if (ga && op == OP_RESID_S0) return hipErrorInvalidValue;   // dense form only (resid_fuses_slab0)
     if (blocks > 0) {
         bool done = false;
         if constexpr (N == 3 && J <= 16 && std::is_same<T, float>::value) {
@@ -674,11 +705,17 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
             else if (op == OP_KEYS)
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+            else if (op == OP_RESID_S0)
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID_S0, false>), dim3(blocks), dim3(256), 0, c->stream, a,
+                                   Gp);
             else
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
         }
     }
-    if (L.nlong > 0 && op != OP_RESID) {
+    // long rows of the sweep and the keys are finished here; the residual has
+    // none to finish, and the first-slab sums of OP_RESID_S0 are finished by
+    // the core sweep (its long-row kernel of the slab statistics)
+    if (L.nlong > 0 && (op == OP_SWEEP || op == OP_KEYS)) {
         if (op == OP_SWEEP)
             hipLaunchKernelGGL((k_rowgroup_long<N, J, T, OP_SWEEP>), dim3(L.nlong), dim3(64), 0, c->stream, a,
                                L.longrows);
@@ -688,6 +725,8 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     }
     return hipGetLastError();
 }
+
+bool resid_fuses_slab0(const vest_ctx *c) { return !use_gather(c, c->N - 1, false); }
 
 hipError_t launch_rowgroup(vest_ctx *c, int mode, int op)
 {
