@@ -118,8 +118,7 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
             sl[q] = wi.base + (int64_t)kk * kWave + lane;
             ev[q] = a.e[sl[q]];
-#pragma unroll
-            for (int t = 0; t < J; ++t) mv[q][t] = a.ms[ms_index<J>(sl[q], t)];
+            ms_load<J, T>(a.ms, sl[q], mv[q]);
         }
         bool ok[U];
         T p[U], pp[U];
@@ -229,8 +228,7 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
             sl[q] = wi.base + (int64_t)kk * kWave + lane;
             ev[q] = a.e[sl[q]];
-#pragma unroll
-            for (int t = 0; t < J; ++t) mv[q][t] = a.ms[ms_index<J>(sl[q], t)];
+            ms_load<J, T>(a.ms, sl[q], mv[q]);
             if constexpr (ROWP) {
 #pragma unroll
                 for (int m = 0; m < N - 2; ++m)

@@ -214,13 +214,50 @@ __device__ __forceinline__ void delta_vec2(const CoreBases<T> &G, const T (&ra)[
 
 // Slot-ordered copy of a per-entry factor row, interleaved per wave: the J
 // values of the 64 slots of one (wave, k) step form one contiguous block of
-// 64 J elements, value t of every lane in a 64-element run (slot bases are
-// multiples of 64), so each of the J loads of a wave is one contiguous
-// 256/512-byte transaction inside a single block.
-template <int J>
+// 64 J elements (slot bases are multiples of 64).  Inside the block, 8-byte
+// values (FP64) go value t of every lane in a 64-element run; 4-byte values
+// (FP32) with J even go in pairs, values 2u and 2u + 1 of every lane in a run
+// of 64 pairs.  Either way each load or store of a wave moves one contiguous
+// 512-byte run of a single block.
+template <int J, typename T>
+__host__ __device__ constexpr bool ms_paired() { return sizeof(T) == 4 && J % 2 == 0; }
+
+template <int J, typename T>
 __host__ __device__ __forceinline__ int64_t ms_index(int64_t slot, int t)
 {
-    return (slot >> 6) * (int64_t)(64 * J) + t * 64 + (slot & 63);
+    if constexpr (ms_paired<J, T>())
+        return (slot >> 6) * (int64_t)(64 * J) + (t >> 1) * 128 + (slot & 63) * 2 + (t & 1);
+    else
+        return (slot >> 6) * (int64_t)(64 * J) + t * 64 + (slot & 63);
+}
+
+template <int J, typename T>
+__device__ __forceinline__ void ms_load(const T *__restrict__ ms, int64_t slot, T (&v)[J])
+{
+    if constexpr (ms_paired<J, T>()) {
+#pragma unroll
+        for (int u = 0; u < J / 2; ++u) {
+            const float2 x = *reinterpret_cast<const float2 *>(ms + ms_index<J, T>(slot, 2 * u));
+            v[2 * u] = x.x;
+            v[2 * u + 1] = x.y;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < J; ++t) v[t] = ms[ms_index<J, T>(slot, t)];
+    }
+}
+
+template <int J, typename T>
+__device__ __forceinline__ void ms_store(T *__restrict__ ms, int64_t slot, const T (&v)[J])
+{
+    if constexpr (ms_paired<J, T>()) {
+#pragma unroll
+        for (int u = 0; u < J / 2; ++u)
+            *reinterpret_cast<float2 *>(ms + ms_index<J, T>(slot, 2 * u)) = float2{v[2 * u], v[2 * u + 1]};
+    } else {
+#pragma unroll
+        for (int t = 0; t < J; ++t) ms[ms_index<J, T>(slot, t)] = v[t];
+    }
 }
 
 // Load a factor row of J values with the widest aligned vector loads.

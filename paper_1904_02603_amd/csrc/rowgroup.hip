@@ -235,12 +235,15 @@ __device__ __forceinline__ void pair_steps(const RowArgs<N, J, T> &a, const Core
             const int64_t slc = hb ? slb : sla;
             a.e[sla] = ea;
             a.e[slc] = hb ? eb : ea;
+            T wa[J], wc[J];
 #pragma unroll
             for (int t = 0; t < J; ++t) {
-                const T va = oka ? ra[N - 2][t] : T(0), vb = okb ? rb[N - 2][t] : T(0);
-                a.ms[ms_index<J>(sla, t)] = va;
-                a.ms[ms_index<J>(slc, t)] = hb ? vb : va;
+                wa[t] = oka ? ra[N - 2][t] : T(0);
+                const T vb = okb ? rb[N - 2][t] : T(0);
+                wc[t] = hb ? vb : wa[t];
             }
+            ms_store<J, T>(a.ms, sla, wa);
+            ms_store<J, T>(a.ms, slc, wc);
         }
 #pragma unroll
         for (int m = 0; m < N - 1; ++m) {
@@ -325,8 +328,10 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
         if (ci[0] < 0) {
             if constexpr (OP == OP_RESID || OP == OP_RESID_S0) {
                 a.e[sl] = T(0);
+                T z[J];
 #pragma unroll
-                for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = T(0);
+                for (int t = 0; t < J; ++t) z[t] = T(0);
+                ms_store<J, T>(a.ms, sl, z);
             }
         } else {
             T r[N - 1][J];
@@ -366,8 +371,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
                 } else {
                     const T ev = x - b;
                     a.e[sl] = ev;
-#pragma unroll
-                    for (int t = 0; t < J; ++t) a.ms[ms_index<J>(sl, t)] = r[N - 2][t];
+                    ms_store<J, T>(a.ms, sl, r[N - 2]);
                     if constexpr (OP == OP_RESID_S0) {
                         // first slab (leading digits 0): w_t = prod_m a^(m)_{i_m 0} a^(N-2)_{i t},
                         // accumulated as the slab pass does
