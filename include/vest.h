@@ -126,7 +126,11 @@ int vest_sweep_core(vest_ctx *ctx);
  * Eq. 3 does when RE > 0.  Marked elements get +infinity.
  *   core_key     prod(J_n) FP64 out
  *   factor_key   host array of N device pointers, I_n*J_n FP64 out each
- * The buffers must stay valid until the next vest_prune. */
+ * The buffers must stay valid until the next vest_prune.  From 2^20 entries
+ * the core keys run on a second stream that the context creates on first use
+ * (forked from and joined back into the context's stream with events, so the
+ * keys are complete in the order of the context's stream, as for every call);
+ * vest_destroy releases it. */
 int vest_responsibility(vest_ctx *ctx, double *core_key, double *const *factor_key);
 
 /* Prune (Sec. 3.3, Alg. 3 last step): in the core and in each factor matrix

@@ -153,6 +153,7 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     int na = nacc_vc(J) > 2 * J ? nacc_vc(J) : 2 * J;
     na = na > keys_nacc(N, J, (int)ts) ? na : keys_nacc(N, J, (int)ts);
     c->partials = (double *)take(p.chunk_bound * na * 8);
+    c->partials_side = (double *)take(p.chunk_bound * na * 8);
     c->red = (double *)take((16 * kLossBlocks + 64) * 8);
     c->flags = (int32_t *)take(64);
     c->sel_hist = (uint32_t *)take((size_t)(VEST_MAX_ORDER + 1) * 4096 * 4);
@@ -396,13 +397,33 @@ int vest_responsibility(vest_ctx *c, double *core_key, double *const *factor_key
     for (int n = 0; n < c->N; ++n)
         if (!factor_key[n]) { set_error("null factor key pointer (mode %d)", n); return VEST_EINVAL; }
     if ((rc = ensure_residual(c))) return rc;
-    for (int n = 0; n < c->N; ++n) {
-        c->key_fac[n] = factor_key[n];
+    for (int n = 0; n < c->N; ++n)
         if ((rc = ensure_gp(c, n))) return rc;
-        CALL_HIP(c, launch_rowgroup(c, n, OP_KEYS), "factor keys");
+    // The core keys stream the entries (HBM-bound) while the factor keys are
+    // bound by the vector ALU; they share no buffer they write (the core keys
+    // take their own long-row partials), so for large contexts they run on a
+    // second stream, forked from and joined back into the context's stream.
+    const bool two = c->d.nnz >= kSideStreamMinNnz;
+    if (two && !c->side) {
+        CALL_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
+        CALL_HIP(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "fork event");
+        CALL_HIP(c, hipEventCreateWithFlags(&c->join, hipEventDisableTiming), "join event");
     }
     c->key_core = core_key;
-    CALL_HIP(c, launch_core_keys(c, core_key), "core keys");
+    if (two) {
+        CALL_HIP(c, hipEventRecord(c->fork, c->stream), "fork");
+        CALL_HIP(c, hipStreamWaitEvent(c->side, c->fork, 0), "fork wait");
+        CALL_HIP(c, launch_core_keys(c, core_key, c->side, c->partials_side), "core keys");
+        CALL_HIP(c, hipEventRecord(c->join, c->side), "join");
+    }
+    for (int n = 0; n < c->N; ++n) {
+        c->key_fac[n] = factor_key[n];
+        CALL_HIP(c, launch_rowgroup(c, n, OP_KEYS), "factor keys");
+    }
+    if (two)
+        CALL_HIP(c, hipStreamWaitEvent(c->stream, c->join, 0), "join wait");
+    else
+        CALL_HIP(c, launch_core_keys(c, core_key, c->stream, c->partials), "core keys");
     c->keys_pending = true;
     return VEST_OK;
 }
@@ -637,6 +658,13 @@ int vest_destroy(vest_ctx *c)
 {
     if (!c) return VEST_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
+    if (c->side) {
+        const hipError_t e2 = hipStreamSynchronize(c->side);
+        if (e == hipSuccess) e = e2;
+        (void)hipStreamDestroy(c->side);
+        (void)hipEventDestroy(c->fork);
+        (void)hipEventDestroy(c->join);
+    }
     if (c->slab_ev) drop_slab_events(c);
     delete c;
     if (e != hipSuccess) return device_error(nullptr, e, "destroy");

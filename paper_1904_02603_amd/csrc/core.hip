@@ -600,13 +600,12 @@ __global__ void __launch_bounds__(256) k_corekeys(const double *__restrict__ P, 
 }
 
 template <int N, int J, typename T, bool WITH_D>
-static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out)
+static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out, hipStream_t st)
 {
     constexpr int SB = key_slabs(N, J, WITH_D, (int)sizeof(T));
     constexpr int PER = WITH_D ? 2 * J : J;
     constexpr int W1 = round8(PER * SB), W2 = round8(2 * J);   // kp2 rows are [a | a^2] in both forms
     const ModeLayout &L = c->lay[N - 1];
-    hipStream_t st = c->stream;
     const int64_t Ilast = c->d.dims[N - 1];
     const int blocks = (L.nwaves + 3) / 4;
     const int64_t gchunks = (Ilast + kGramRows - 1) / kGramRows;
@@ -624,7 +623,7 @@ static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out)
         if (blocks > 0)
             hipLaunchKernelGGL((k_slabkeys<N, J, T, SB, WITH_D>), dim3(blocks), dim3(256), 0, st, a, nsb);
         if (L.nlong > 0)
-            hipLaunchKernelGGL(k_slab_long<PER * SB>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
+            hipLaunchKernelGGL(k_slab_long<PER * SB>, dim3(L.nlong), dim3(64), 0, st, a.partials, L.longrows,
                                c->rowbuf, c->ldrb);
         hipLaunchKernelGGL((k_gram<W1, W2>), dim3((unsigned)gchunks), dim3(gram_threads<W1>()), 0, st, c->rowbuf, c->ldrb, c->kp, W2,
                            Ilast, c->gram_part);
@@ -637,12 +636,12 @@ static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out)
 }
 
 template <int N, int J, typename T>
-static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab0_done)
+static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab0_done, hipStream_t st,
+                              double *partials)
 {
     const int last = N - 1;
     const ModeLayout &L = c->lay[last];
     constexpr int GW = gram_width(J);
-    hipStream_t st = c->stream;
     const int64_t Ilast = c->d.dims[last];
 
     SlabArgs<N, J, T> a{};
@@ -664,7 +663,7 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
     a.dprev = c->dprev;
     a.rowbuf = c->rowbuf;
     a.ldrb = c->ldrb;
-    a.partials = c->partials;
+    a.partials = partials;
 
     const int blocks = (L.nwaves + 3) / 4;
     const int64_t gchunks = (Ilast + kGramRows - 1) / kGramRows;
@@ -677,9 +676,9 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
     };
     if (keys) {
         if (c->hdiag_valid)
-            core_keys_batches<N, J, T, false>(c, a, key_out);
+            core_keys_batches<N, J, T, false>(c, a, key_out, st);
         else
-            core_keys_batches<N, J, T, true>(c, a, key_out);
+            core_keys_batches<N, J, T, true>(c, a, key_out, st);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_kp<J>, dim3((unsigned)((Ilast + 255) / 256)), dim3(256), 0, st, c->A[last], Ilast, GW,
@@ -696,7 +695,7 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
             if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n++ + 1], st);
         }
         if (L.nlong > 0)
-            hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, c->partials, L.longrows,
+            hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, partials, L.longrows,
                                c->rowbuf, c->ldrb);
         hipLaunchKernelGGL((k_gram<GW, GW>), dim3((unsigned)gchunks), dim3(gram_threads<GW>()), 0, st, c->rowbuf, c->ldrb, c->kp, GW,
                            Ilast, c->gram_part);
@@ -713,19 +712,26 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
     return hipGetLastError();
 }
 
-static hipError_t core_pass(vest_ctx *c, bool keys, double *key_out, bool slab0_done)
+static hipError_t core_pass(vest_ctx *c, bool keys, double *key_out, bool slab0_done, hipStream_t st,
+                           double *partials)
 {
-#define VEST_CASE(NN, JJ)                                                                \
-    if (c->N == NN && c->J == JJ)                                                        \
-        return c->f32 ? core_pass_t<NN, JJ, float>(c, keys, key_out, slab0_done) \
-                                           : core_pass_t<NN, JJ, double>(c, keys, key_out, slab0_done);
+#define VEST_CASE(NN, JJ)                                                                              \
+    if (c->N == NN && c->J == JJ)                                                                      \
+        return c->f32 ? core_pass_t<NN, JJ, float>(c, keys, key_out, slab0_done, st, partials)       \
+                      : core_pass_t<NN, JJ, double>(c, keys, key_out, slab0_done, st, partials);
     VEST_SHAPES(VEST_CASE)
 #undef VEST_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_core_sweep(vest_ctx *c, bool slab0_done) { return core_pass(c, false, nullptr, slab0_done); }
-hipError_t launch_core_keys(vest_ctx *c, double *core_key) { return core_pass(c, true, core_key, false); }
+hipError_t launch_core_sweep(vest_ctx *c, bool slab0_done)
+{
+    return core_pass(c, false, nullptr, slab0_done, c->stream, c->partials);
+}
+hipError_t launch_core_keys(vest_ctx *c, double *core_key, hipStream_t st, double *partials)
+{
+    return core_pass(c, true, core_key, false, st, partials);
+}
 
 bool shape_supported(int N, int J)
 {

@@ -40,6 +40,7 @@ constexpr int kLaneTarget = 16;                   // entries per lane in a row g
 constexpr int kChunk = kWave * kLaneTarget;       // entries per long-row chunk
 constexpr int kGramRows = 128;                    // rows per gram partial
 constexpr int kLossBlocks = 1024;                 // fixed grid of the loss reductions
+constexpr int64_t kSideStreamMinNnz = 1 << 20;    // entries from which the key passes overlap
 
 struct WaveInfo {
     int64_t base;   // slot of (k = 0, lane 0)
@@ -161,6 +162,7 @@ struct vest_ctx {
     double *gram = nullptr;           // [gw*gw]
     double *dprev = nullptr;          // [J*J] last slab's core change
     double *partials = nullptr;       // long-row chunk partials
+    double *partials_side = nullptr;  // ... of the core keys while they run on `side`
     double *red = nullptr;            // reduction scratch [4 * kLossBlocks + 16]
     int32_t *flags = nullptr;         // device error flags [16]
     uint32_t *pv_in = nullptr, *pv_out = nullptr;  // nonzero flags / positions (export)
@@ -191,6 +193,11 @@ struct vest_ctx {
     bool dead = false;
     hipEvent_t *slab_ev = nullptr;    // vest_slab_timing: start / end event pairs
     int slab_ev_cap = 0, slab_ev_n = 0;
+    // vest_responsibility runs the core keys (HBM-bound) on a second stream
+    // beside the factor keys (ALU-bound); created on first use for large
+    // contexts only
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace vest {
@@ -210,7 +217,7 @@ hipError_t launch_value_keys(vest_ctx *c, double *core_key, double *const *fkey)
 // Live entries of the mode-0 layout re-assembled into (idx, val) in `stage`;
 // *live and *dead_sq (sum X^2 of the dropped ones) on return (synchronises).
 hipError_t launch_compact(vest_ctx *c, int32_t **idx, double **val, int64_t *live, double *dead_sq);
-hipError_t launch_core_keys(vest_ctx *c, double *core_key);
+hipError_t launch_core_keys(vest_ctx *c, double *core_key, hipStream_t st, double *partials);
 hipError_t launch_permute_core(vest_ctx *c, int mode);
 hipError_t launch_gather_copy(vest_ctx *c, int mode);
 hipError_t launch_loss(vest_ctx *c, double *dev_out3);          // sse, reg (device)

@@ -11,6 +11,10 @@
 * Order-4 Zipf tensor (the 50k x 50k x 1000 x 24 workload scaled down to
   300 x 300 x 40 x 24, 2e4 entries, ranks 8): iterations with responsibility
   and prune steps up to 85 % marked, FP64, masks identical after every prune.
+* 1.2e6 entries over 300 x 200 x 2000 (Zipf last mode, rows up to ~6e4
+  entries, ranks 5): large enough that the core keys run on the context's
+  second stream beside the factor keys, long rows in every mode; keys,
+  masks and the next iteration against the oracle.
 """
 import numpy as np
 import pytest
@@ -82,6 +86,29 @@ def test_order4_zipf_tensor_pruned_to_85_percent():
         assert np.array_equal(g.cmask.cpu().numpy().astype(bool), o.cmask.astype(bool))
         for n, m in enumerate(g.factor_masks_bool()):
             assert np.array_equal(m.cpu().numpy(), o.fmask[n].astype(bool)), (t, n)
+    g.iteration()
+    o.iteration()
+    assert_state(g, o, what="after pruning")
+
+
+def test_keys_on_two_streams_with_long_rows_match_oracle():
+    p = synth.make_problem((300, 200, 2000), 1_200_000, (5, 5, 5), 93, zipf=(None, None, 1.1), noise_var=0.01)
+    g, o = pair(p, REG_L1, 0.3)
+    g.iteration()
+    o.iteration()
+    assert_state(g, o, what="iteration")
+    gck, gfk = g.responsibility()
+    ock, ofk = o.responsibility()
+    keys_close(gck, ock, "core keys")
+    for n in range(3):
+        keys_close(gfk[n], ofk[n], "factor keys %d" % n)
+    kc, kf = 40, [450, 300, 3000]
+    g.prune(kc, kf)
+    o.prune(ock, ofk, kc, kf)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cmask.cpu().numpy().astype(bool), o.cmask.astype(bool))
+    for n, m in enumerate(g.factor_masks_bool()):
+        assert np.array_equal(m.cpu().numpy(), o.fmask[n].astype(bool)), n
     g.iteration()
     o.iteration()
     assert_state(g, o, what="after pruning")
