@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
         for (int q = 0; q < U; ++q) {
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
 #pragma unroll
-            for (int m = 0; m < NI; ++m) dst[q][m] = a.oidx[m][wi.base + (int64_t)kk * kWave + lane];
+            for (int m = 0; m < NI; ++m) dst[q][m] = ld_stream(a.oidx[m] + wi.base + (int64_t)kk * kWave + lane);
         }
     };
     if (wi.K > 0) load_idx(0, ii);
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
         for (int q = 0; q < U; ++q) {
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
             sl[q] = wi.base + (int64_t)kk * kWave + lane;
-            ev[q] = a.e[sl[q]];
+            ev[q] = ld_stream(a.e + sl[q]);
             ms_load<J, T>(a.ms, sl[q], mv[q]);
         }
         bool ok[U];
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 #pragma unroll
                 for (int t = 1; t < J; ++t) du = vfma(mv[q][t], u[t], du);
                 e -= pp[q] * du;
-                if (ok[q]) a.e[sl[q]] = e;
+                if (ok[q]) st_stream(e, a.e + sl[q]);
             }
             if constexpr (ACC) {
                 T w[J];
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
         for (int q = 0; q < U; ++q) {
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
 #pragma unroll
-            for (int m = 0; m < NI; ++m) dst[q][m] = a.oidx[m][wi.base + (int64_t)kk * kWave + lane];
+            for (int m = 0; m < NI; ++m) dst[q][m] = ld_stream(a.oidx[m] + wi.base + (int64_t)kk * kWave + lane);
         }
     };
     if (wi.K > 0) load_idx(0, ii);
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
         for (int q = 0; q < U; ++q) {
             const int kk = k0 + q < wi.K ? k0 + q : wi.K - 1;
             sl[q] = wi.base + (int64_t)kk * kWave + lane;
-            ev[q] = a.e[sl[q]];
+            ev[q] = ld_stream(a.e + sl[q]);
             ms_load<J, T>(a.ms, sl[q], mv[q]);
             if constexpr (ROWP) {
 #pragma unroll

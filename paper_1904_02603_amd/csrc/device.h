@@ -231,19 +231,29 @@ __host__ __device__ __forceinline__ int64_t ms_index(int64_t slot, int t)
         return (slot >> 6) * (int64_t)(64 * J) + t * 64 + (slot & 63);
 }
 
+// Streams that every pass reads or writes once (entry indices, values, the
+// residual, the slot copy of factor rows: hundreds of MB) go through the
+// non-temporal hint, so that they do not evict the cache lines of the factor
+// rows and columns that the same kernels gather.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_stream(T v, T *p) { __builtin_nontemporal_store(v, p); }
+
 template <int J, typename T>
 __device__ __forceinline__ void ms_load(const T *__restrict__ ms, int64_t slot, T (&v)[J])
 {
     if constexpr (ms_paired<J, T>()) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int u = 0; u < J / 2; ++u) {
-            const float2 x = *reinterpret_cast<const float2 *>(ms + ms_index<J, T>(slot, 2 * u));
+            const f2 x = ld_stream(reinterpret_cast<const f2 *>(ms + ms_index<J, T>(slot, 2 * u)));
             v[2 * u] = x.x;
             v[2 * u + 1] = x.y;
         }
     } else {
 #pragma unroll
-        for (int t = 0; t < J; ++t) v[t] = ms[ms_index<J, T>(slot, t)];
+        for (int t = 0; t < J; ++t) v[t] = ld_stream(ms + ms_index<J, T>(slot, t));
     }
 }
 
@@ -251,12 +261,15 @@ template <int J, typename T>
 __device__ __forceinline__ void ms_store(T *__restrict__ ms, int64_t slot, const T (&v)[J])
 {
     if constexpr (ms_paired<J, T>()) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int u = 0; u < J / 2; ++u)
-            *reinterpret_cast<float2 *>(ms + ms_index<J, T>(slot, 2 * u)) = float2{v[2 * u], v[2 * u + 1]};
+        for (int u = 0; u < J / 2; ++u) {
+            const f2 x = {v[2 * u], v[2 * u + 1]};
+            st_stream(x, reinterpret_cast<f2 *>(ms + ms_index<J, T>(slot, 2 * u)));
+        }
     } else {
 #pragma unroll
-        for (int t = 0; t < J; ++t) ms[ms_index<J, T>(slot, t)] = v[t];
+        for (int t = 0; t < J; ++t) st_stream(v[t], ms + ms_index<J, T>(slot, t));
     }
 }
 

@@ -187,11 +187,11 @@ __device__ __forceinline__ void pair_steps(const RowArgs<N, J, T> &a, const Core
         const int64_t s1 = wi.base + (int64_t)(k + 1 < K ? k + 1 : K - 1) * kWave + lane;
 #pragma unroll
         for (int m = 0; m < N - 1; ++m) {
-            i0[m] = a.oidx[m][s0];
-            i1[m] = a.oidx[m][s1];
+            i0[m] = ld_stream(a.oidx[m] + s0);
+            i1[m] = ld_stream(a.oidx[m] + s1);
         }
-        x0 = a.xval[s0];
-        x1 = a.xval[s1];
+        x0 = ld_stream(a.xval + s0);
+        x1 = ld_stream(a.xval + s1);
     };
     if (K > 0) load_pair(0, ia, xa, ib, xb);
 #pragma unroll 1
@@ -233,8 +233,8 @@ __device__ __forceinline__ void pair_steps(const RowArgs<N, J, T> &a, const Core
             // without a partner the second store repeats the first (same
             // lane, same values), so both contractions stay unconditional
             const int64_t slc = hb ? slb : sla;
-            a.e[sla] = ea;
-            a.e[slc] = hb ? eb : ea;
+            st_stream(ea, a.e + sla);
+            st_stream(hb ? eb : ea, a.e + slc);
             T wa[J], wc[J];
 #pragma unroll
             for (int t = 0; t < J; ++t) {
@@ -303,8 +303,8 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
     auto load_step = [&](int k, int32_t (&ii)[N - 1], T &x) {
         const int64_t sl = wi.base + (int64_t)(k < K ? k : K - 1) * kWave + lane;
 #pragma unroll
-        for (int m = 0; m < N - 1; ++m) ii[m] = a.oidx[m][sl];
-        x = a.xval[sl];
+        for (int m = 0; m < N - 1; ++m) ii[m] = ld_stream(a.oidx[m] + sl);
+        x = ld_stream(a.xval + sl);
     };
     auto load_marks = [&](const int32_t (&ii)[N - 1], uint32_t (&mm)[N - 1]) {
 #pragma unroll
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
         if constexpr (GA) load_marks(pi, nm);
         if (ci[0] < 0) {
             if constexpr (OP == OP_RESID || OP == OP_RESID_S0) {
-                a.e[sl] = T(0);
+                st_stream(T(0), a.e + sl);
                 T z[J];
 #pragma unroll
                 for (int t = 0; t < J; ++t) z[t] = T(0);
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
                     }
                 } else {
                     const T ev = x - b;
-                    a.e[sl] = ev;
+                    st_stream(ev, a.e + sl);
                     ms_store<J, T>(a.ms, sl, r[N - 2]);
                     if constexpr (OP == OP_RESID_S0) {
                         // first slab (leading digits 0): w_t = prod_m a^(m)_{i_m 0} a^(N-2)_{i t},
@@ -537,15 +537,15 @@ __global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, c
 
     for (int k = 0; k < wi.K; ++k) {
         const int64_t sl = wi.base + (int64_t)k * kWave + lane;
-        const int32_t i0 = a.oidx[0][sl];
-        const int32_t i1 = a.oidx[1][sl];  // 0 on padding slots
+        const int32_t i0 = ld_stream(a.oidx[0] + sl);
+        const int32_t i1 = ld_stream(a.oidx[1] + sl);  // 0 on padding slots
         const bool ok = i0 >= 0;
         float rp[J], rq[J];
         load_grow<J, float>(a.fac[0] + (int64_t)(ok ? i0 : 0) * gather_ld(J, 4), rp);
         load_grow<J, float>(a.fac[1] + (int64_t)i1 * gather_ld(J, 4), rq);
 #pragma unroll
         for (int t = 0; t < J; ++t) rq[t] = ok ? rq[t] : 0.0f;  // zero column: T = 0, delta = 0
-        const float x = a.xval[sl];                               // 0 on padding slots
+        const float x = ld_stream(a.xval + sl);                               // 0 on padding slots
 
         // B operands of the two batches from the lane's own row: lane l of
         // batch b must hold K range h of the entry of lane 32 b + (l & 31).
