@@ -199,8 +199,9 @@ int vest_compact(vest_ctx *ctx, int64_t *live);
  *                       values are nonzero and whose core column
  *                       G[.., j_n = any, ..] is nonzero; the core is staged in
  *                       LDS
- * Both forms compute the same sums up to rounding order.  VEST_EINVAL for an
- * unknown value. */
+ * Both forms compute the same sums up to rounding order.  From order 8 the
+ * dense form is not compiled and every setting runs the gather form.
+ * VEST_EINVAL for an unknown value. */
 enum { VEST_KERNEL_AUTO = 0, VEST_KERNEL_DENSE = 1, VEST_KERNEL_GATHER = 2 };
 int vest_set_kernel(vest_ctx *ctx, int32_t kernel);
 

@@ -149,6 +149,27 @@ struct FacIn {
     const T *p[VEST_MAX_ORDER];
 };
 
+// One level of the looped contraction over the other modes' indices
+// o_L (order-8 shapes, where the unrolled dense form is not compiled): the
+// running product w of the factor values chosen so far, o the flat index of
+// the indices chosen so far.
+template <int L, int N, int J, typename T>
+__device__ __forceinline__ void heldout_level(const T *__restrict__ Gp, const T (&r)[N - 1][J], T w, int o, T (&d)[J])
+{
+    constexpr int S = ipow(J, N - 1);
+#pragma nounroll
+    for (int b = 0; b < J; ++b) {
+        const T v = w * pick<J, T>(r[L], b);
+        const int oo = o * J + b;
+        if constexpr (L == N - 2) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) d[j] = vfma(v, Gp[j * S + oo], d[j]);
+        } else {
+            heldout_level<L + 1, N, J, T>(Gp, r, v, oo, d);
+        }
+    }
+}
+
 // B(alpha) = a^(0)_{i_0} . delta^(0)_alpha (Eq. 7) for entries outside the
 // layouts; per-block partial sums of (X - B)^2 and X^2, then a fixed-order
 // total.  Out-of-range indices raise a flag instead of being read.
@@ -178,7 +199,15 @@ __global__ void __launch_bounds__(256) k_heldout(const int32_t *__restrict__ idx
         T own[J];
         load_grow<J, T>(fac.p[0] + (int64_t)ii[0] * gather_ld(J, sizeof(T)), own);
         T d[J];
-        delta_vec<N, J, T>(Gb, r, d);
+        if constexpr (dense_form(N, J)) {
+            delta_vec<N, J, T>(Gb, r, d);
+        } else {
+            // looped form: delta_j = sum_o Gp[j][o] prod_k r[k][o_k], o in flat
+            // order over the other modes (mode 0's permuted core is row-major)
+#pragma unroll
+            for (int j = 0; j < J; ++j) d[j] = T(0);
+            heldout_level<0, N, J, T>(Gp, r, T(1), 0, d);
+        }
         T b = own[0] * d[0];
 #pragma unroll
         for (int t = 1; t < J; ++t) b = vfma(own[t], d[t], b);

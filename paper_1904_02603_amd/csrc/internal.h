@@ -31,7 +31,12 @@
 
 // (order, uniform rank) pairs with compiled kernel instances.
 #define VEST_SHAPES(X) X(2, 2) X(2, 3) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 8) X(3, 10) \
-    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(5, 3) X(6, 3) X(7, 3)
+    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(5, 3) X(6, 3) X(7, 3) X(8, 3)
+
+// The dense contraction of Eq. 11 is unrolled per (N, J); from order 8 it is
+// not instantiated and every factor pass runs the looped gather form over the
+// core staged in LDS (J^N values: 52 KB in FP64 at N = 8, J = 3).
+__host__ __device__ constexpr bool dense_form(int N, int J) { return N <= 7 && J > 0; }
 
 namespace vest {
 

@@ -637,6 +637,7 @@ __global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, c
 // J d_k (d_k = unmarked fraction of A^(k)).
 static bool use_gather(const vest_ctx *c, int mode, bool dense_on_mfma)
 {
+    if (!dense_form(c->N, c->J)) return true;
     if (c->kernel_policy == VEST_KERNEL_DENSE) return false;
     if (c->kernel_policy == VEST_KERNEL_GATHER) return true;
     const int N = c->N, J = c->J;
@@ -704,7 +705,7 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
             else
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
-        } else {
+        } else if constexpr (dense_form(N, J)) {
             if (op == OP_SWEEP)
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
             else if (op == OP_KEYS)
@@ -714,6 +715,8 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
                                    Gp);
             else
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
+        } else {
+            return hipErrorInvalidValue;  // unreachable: use_gather is true without a dense instance
         }
     }
     // long rows of the sweep and the keys are finished here; the residual has

@@ -1,10 +1,12 @@
-"""GPU parity at orders 5 to 7 (ranks 3), the shapes of the order-scaling
+"""GPU parity at orders 5 to 8 (ranks 3), the shapes of the order-scaling
 workload (the paper's runtime against tensor order, Fig. 4a).
 
 Same bar as the order-3 / order-4 parity: FP64 factors, core, loss and keys
 within 1e-10 of the oracle, prune masks identical; the FP32 form's loss within
 1e-6 after an iteration.  At order 7 the core has 2187 elements, so the core
-sweep runs 243 slab passes and the core keys several batches.
+sweep runs 243 slab passes and the core keys several batches.  At order 8
+(6561 core elements, 729 slab passes) every factor pass runs the looped
+gather contraction, and the held-out error its looped core product.
 """
 import numpy as np
 import pytest
@@ -19,8 +21,9 @@ ORDERS = [
     ((9, 8, 7, 6, 8), 1500),
     ((7, 6, 6, 5, 6, 7), 1500),
     ((6, 5, 5, 4, 4, 5, 6), 1200),
+    ((5, 4, 4, 4, 3, 4, 4, 5), 1000),
 ]
-IDS = ["N5J3", "N6J3", "N7J3"]
+IDS = ["N5J3", "N6J3", "N7J3", "N8J3"]
 
 
 @pytest.mark.parametrize("reg", [REG_LF, REG_L1], ids=["LF", "L1"])
@@ -68,3 +71,28 @@ def test_order6_fp32_form_tracks_oracle():
     gap = abs(gl["loss"] - ol["loss"]) / ol["loss"]
     say("order-6 FP32 loss gap %.3e" % gap)
     assert gap <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32"])
+def test_order8_held_out_error_and_fp32_form(prec):
+    v = V()
+    dims, nnz = ORDERS[3]
+    p = make(dims, (3,) * len(dims), nnz, 94)
+    rng = np.random.default_rng(95)
+    test = rng.random(nnz) < 0.1
+    tr = dict(p, idx=p["idx"][~test], val=p["val"][~test])
+    g, o = pair(tr, REG_LF, 0.05, precision=getattr(v, prec))
+    g.iteration()
+    o.iteration()
+    gl, ol = g.loss(), o.loss()
+    # FP32: the FP32 forms' tolerance (1e-4).  At order 8 every delta is a
+    # sum of 2187 FP32 column terms (order 6: 729 in the dense form), and the
+    # loss gap measured here is about 1e-5.
+    bar = 1e-10 if prec == "FP64" else 1e-4
+    say(prec, "order-8 loss gap %.3e" % (abs(gl["loss"] - ol["loss"]) / ol["loss"]))
+    assert abs(gl["loss"] - ol["loss"]) <= bar * ol["loss"]
+    from oracle.oracle import Oracle
+    ge = g.test_error(p["idx"][test], p["val"][test])
+    ot = Oracle(p["idx"][test], p["val"][test], o.factors, o.core, reg=REG_LF, lam=0.05).loss()
+    say(prec, "order-8 test RE gpu %.12f oracle %.12f" % (ge["re"], ot["re"]))
+    assert abs(ge["sse"] - ot["sse"]) <= bar * ot["sse"]
