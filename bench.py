@@ -321,13 +321,13 @@ def source_hash(files):
 def scaling_study(iters=3, warmup=1):
     """Time per Alg. 2 iteration (all factor sweeps + core sweep + loss) on the
     synthetic tensors of the paper's scalability runs (Sec. 4, Fig. 4a-c),
-    ranks 3, FP64: (a) order 3..8 at dimensionality and |Omega| 10^3 (orders 9
-    and 10 have no kernel instance), (b) dimensionality 10^3..10^8 at order 3
+    ranks 3, FP64: (a) order 3..10 at dimensionality and |Omega| 10^3,
+    (b) dimensionality 10^3..10^8 at order 3
     with |Omega| equal to it, (c) |Omega| 10^3..10^7 at order 3, dimensionality
     10^3."""
     import torch
     from paper_1904_02603_amd import synth, vest
-    runs = {"order": [(N, 10 ** 3, 10 ** 3) for N in range(3, 9)],
+    runs = {"order": [(N, 10 ** 3, 10 ** 3) for N in range(3, 11)],
             "dimensionality": [(3, 10 ** e, 10 ** e) for e in range(3, 9)],
             "entries": [(3, 10 ** 3, 10 ** e) for e in range(3, 8)]}
     out = {}

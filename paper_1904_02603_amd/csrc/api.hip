@@ -154,6 +154,10 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     na = na > keys_nacc(N, J, (int)ts) ? na : keys_nacc(N, J, (int)ts);
     c->partials = (double *)take(p.chunk_bound * na * 8);
     c->partials_side = (double *)take(p.chunk_bound * na * 8);
+    if (!gather_in_lds(N, J, (int)ts)) {
+        c->gt = take((size_t)c->G * ts);
+        c->gnz = (uint32_t *)take(((size_t)(c->G / J) + 31) / 32 * 4);
+    }
     c->red = (double *)take((16 * kLossBlocks + 64) * 8);
     c->flags = (int32_t *)take(64);
     c->sel_hist = (uint32_t *)take((size_t)(VEST_MAX_ORDER + 1) * 4096 * 4);

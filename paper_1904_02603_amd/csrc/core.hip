@@ -49,7 +49,7 @@ struct SlabArgs {
     double *rowbuf;               // [I_{N-1}][ldrb]
     int32_t ldrb;
     double *partials;
-    int32_t blead[kKeyAccMax * NL];  // k_slabkeys: leading indices of each slab of the batch
+    int32_t blead[kKeyAccMax / 2 * NL];  // k_slabkeys: leading indices of each slab of the batch
 };
 
 // The mode N-2 factor row of every entry is read from the slot-ordered copy
@@ -605,6 +605,7 @@ static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out,
     constexpr int SB = key_slabs(N, J, WITH_D, (int)sizeof(T));
     constexpr int PER = WITH_D ? 2 * J : J;
     constexpr int W1 = round8(PER * SB), W2 = round8(2 * J);   // kp2 rows are [a | a^2] in both forms
+    static_assert(SB <= kKeyAccMax / 2, "leading indices of a batch fit SlabArgs::blead");
     const ModeLayout &L = c->lay[N - 1];
     const int64_t Ilast = c->d.dims[N - 1];
     const int blocks = (L.nwaves + 3) / 4;

@@ -54,6 +54,20 @@ struct CoreBases {
 };
 
 template <int N, int J, typename T>
+__device__ __forceinline__ CoreBases<T> core_bases(const T *__restrict__ Gp);
+
+// The bases only where the dense contraction reads them (an empty set for the
+// gather form, whose core may exceed the 64 windows).
+template <int N, int J, typename T, bool USE>
+__device__ __forceinline__ CoreBases<T> core_bases_if(const T *__restrict__ Gp)
+{
+    if constexpr (USE)
+        return core_bases<N, J, T>(Gp);
+    else
+        return CoreBases<T>{};
+}
+
+template <int N, int J, typename T>
 __device__ __forceinline__ CoreBases<T> core_bases(const T *__restrict__ Gp)
 {
     constexpr int W = CoreBases<T>::W;

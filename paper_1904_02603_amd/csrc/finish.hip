@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_heldout(const int32_t *__restrict__ idx
                                                   double *__restrict__ part, int32_t *__restrict__ flag)
 {
     __shared__ double s1[256], s2[256];
-    const CoreBases<T> Gb = core_bases<N, J, T>(Gp);
+    const CoreBases<T> Gb = core_bases_if<N, J, T, dense_form(N, J)>(Gp);
     double e2 = 0.0, x2 = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
         int32_t ii[N];

@@ -31,11 +31,10 @@
 
 // (order, uniform rank) pairs with compiled kernel instances.
 #define VEST_SHAPES(X) X(2, 2) X(2, 3) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 8) X(3, 10) \
-    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(5, 3) X(6, 3) X(7, 3) X(8, 3)
+    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(5, 3) X(6, 3) X(7, 3) X(8, 3) X(9, 3) X(10, 3)
 
 // The dense contraction of Eq. 11 is unrolled per (N, J); from order 8 it is
-// not instantiated and every factor pass runs the looped gather form over the
-// core staged in LDS (J^N values: 52 KB in FP64 at N = 8, J = 3).
+// not instantiated and every factor pass runs the looped gather form.
 __host__ __device__ constexpr bool dense_form(int N, int J) { return N <= 7 && J > 0; }
 
 namespace vest {
@@ -95,6 +94,19 @@ __host__ __device__ constexpr int round8(int x) { return (x + 7) / 8 * 8; }
 __host__ __device__ constexpr int gram_width(int J) { return round8(nacc_vc(J)); }
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// The gather form stages the core with the mode-n index innermost plus one bit
+// per core column.  Up to 64 KB it is staged in each workgroup's LDS; larger
+// stagings (orders 9 and 10 at rank 3: 157 KB and 472 KB in FP64) are written
+// once per pass into the workspace and read through the cache.
+__host__ __device__ constexpr size_t gather_stage_bytes(int N, int J, int tsize)
+{
+    return (size_t)ipow(J, N) * tsize + ((size_t)ipow(J, N - 1) + 31) / 32 * 4;
+}
+__host__ __device__ constexpr bool gather_in_lds(int N, int J, int tsize)
+{
+    return gather_stage_bytes(N, J, tsize) <= 65536;
+}
 
 // Core-key passes handle key_slabs(N, J, d, tsize) slabs at once (J or 2 J
 // accumulators each, at most key_acc(tsize) per lane so that nothing spills,
@@ -168,6 +180,8 @@ struct vest_ctx {
     double *dprev = nullptr;          // [J*J] last slab's core change
     double *partials = nullptr;       // long-row chunk partials
     double *partials_side = nullptr;  // ... of the core keys while they run on `side`
+    void *gt = nullptr;               // gather-form core staging when it exceeds LDS (T, [o][j])
+    uint32_t *gnz = nullptr;          // ... and its nonzero-column bits
     double *red = nullptr;            // reduction scratch [4 * kLossBlocks + 16]
     int32_t *flags = nullptr;         // device error flags [16]
     uint32_t *pv_in = nullptr, *pv_out = nullptr;  // nonzero flags / positions (export)

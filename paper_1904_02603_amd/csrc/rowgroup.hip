@@ -43,6 +43,8 @@ struct RowArgs {
     double *keys;             // OP_KEYS: out [I_n * J]
     double *rowbuf;           // OP_RESID_S0: per-row statistics of the first slab
     int32_t ldrb;
+    const T *gt;              // gather form, staging outside LDS: core [o][j] ...
+    const uint32_t *gnz;      // ... and its nonzero-column bits
 };
 
 template <int J, int OP>
@@ -144,7 +146,7 @@ __device__ __forceinline__ void delta_gather(const T *__restrict__ Gt, const uin
 template <int N, int J, typename T>
 __host__ __device__ constexpr size_t gather_lds_bytes()
 {
-    return (size_t)ipow(J, N) * sizeof(T) + ((size_t)ipow(J, N - 1) + 31) / 32 * 4;
+    return gather_in_lds(N, J, (int)sizeof(T)) ? gather_stage_bytes(N, J, (int)sizeof(T)) : 0;
 }
 
 // Block-cooperative staging of the mode-permuted core Gp ([j][o], row-major)
@@ -167,6 +169,13 @@ __device__ __forceinline__ void stage_core(const T *__restrict__ Gp, T *Gt, uint
         if (nz) atomicOr(&Gnz[o >> 5], 1u << (o & 31));
     }
     __syncthreads();
+}
+
+// Gather-form staging in the workspace for cores that exceed LDS: one block.
+template <int N, int J, typename T>
+__global__ void __launch_bounds__(1024) k_stage_core(const T *__restrict__ Gp, T *Gt, uint32_t *Gnz)
+{
+    stage_core<N, J, T>(Gp, Gt, Gnz);
 }
 
 // Dense OP_KEYS / OP_RESID steps, two entries per lane at a time (steps k
@@ -263,10 +272,16 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
 {
     constexpr int NA = row_nacc<J, OP>();
     extern __shared__ __align__(16) char smem[];
-    T *Gt = reinterpret_cast<T *>(smem);
-    uint32_t *Gnz = reinterpret_cast<uint32_t *>(smem + (size_t)ipow(J, N) * sizeof(T));
-    if constexpr (GA) stage_core<N, J, T>(Gp, Gt, Gnz);
-    const CoreBases<T> Gb = core_bases<N, J, T>(Gp);
+    const T *Gt = a.gt;
+    const uint32_t *Gnz = a.gnz;
+    if constexpr (GA && gather_in_lds(N, J, (int)sizeof(T))) {
+        T *g = reinterpret_cast<T *>(smem);
+        uint32_t *nz = reinterpret_cast<uint32_t *>(smem + (size_t)ipow(J, N) * sizeof(T));
+        stage_core<N, J, T>(Gp, g, nz);
+        Gt = g;
+        Gnz = nz;
+    }
+    const CoreBases<T> Gb = core_bases_if<N, J, T, !GA>(Gp);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (wave >= a.nwaves) return;
@@ -685,6 +700,15 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     const int blocks = (L.nwaves + 3) / 4;
     const bool ga = use_gather(c, mode, (N == 3 && J <= 16 && std::is_same<T, float>::value && op == OP_SWEEP));
     const size_t lds = ga ? gather_lds_bytes<N, J, T>() : 0;
+    if constexpr (!gather_in_lds(N, J, (int)sizeof(T))) {
+        if (ga) {
+            if (!c->gt || !c->gnz) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_stage_core<N, J, T>), dim3(1), dim3(1024), 0, c->stream, Gp,
+                               reinterpret_cast<T *>(c->gt), c->gnz);
+            a.gt = reinterpret_cast<const T *>(c->gt);
+            a.gnz = c->gnz;
+        }
+    }
     if (ga && op == OP_RESID_S0) return hipErrorInvalidValue;   // dense form only (resid_fuses_slab0)
     if (blocks > 0) {
         bool done = false;

@@ -1,4 +1,4 @@
-"""GPU parity at orders 5 to 8 (ranks 3), the shapes of the order-scaling
+"""GPU parity at orders 5 to 10 (ranks 3), the shapes of the order-scaling
 workload (the paper's runtime against tensor order, Fig. 4a).
 
 Same bar as the order-3 / order-4 parity: FP64 factors, core, loss and keys
@@ -6,7 +6,9 @@ within 1e-10 of the oracle, prune masks identical; the FP32 form's loss within
 1e-6 after an iteration.  At order 7 the core has 2187 elements, so the core
 sweep runs 243 slab passes and the core keys several batches.  At order 8
 (6561 core elements, 729 slab passes) every factor pass runs the looped
-gather contraction, and the held-out error its looped core product.
+gather contraction, and the held-out error its looped core product; at
+orders 9 and 10 (19683 and 59049 core elements, 2187 and 6561 slab passes)
+the gather form reads the core from a staging in the workspace instead of LDS.
 """
 import numpy as np
 import pytest
@@ -22,8 +24,10 @@ ORDERS = [
     ((7, 6, 6, 5, 6, 7), 1500),
     ((6, 5, 5, 4, 4, 5, 6), 1200),
     ((5, 4, 4, 4, 3, 4, 4, 5), 1000),
+    ((4, 3, 4, 3, 4, 3, 4, 3, 4), 500),
+    ((3, 4, 3, 4, 3, 4, 3, 4, 3, 4), 300),
 ]
-IDS = ["N5J3", "N6J3", "N7J3", "N8J3"]
+IDS = ["N5J3", "N6J3", "N7J3", "N8J3", "N9J3", "N10J3"]
 
 
 @pytest.mark.parametrize("reg", [REG_LF, REG_L1], ids=["LF", "L1"])
@@ -74,9 +78,10 @@ def test_order6_fp32_form_tracks_oracle():
 
 
 @pytest.mark.parametrize("prec", ["FP64", "FP32"])
-def test_order8_held_out_error_and_fp32_form(prec):
+@pytest.mark.parametrize("case", [ORDERS[3], ORDERS[5]], ids=["N8J3", "N10J3"])
+def test_large_order_held_out_error_and_fp32_form(case, prec):
     v = V()
-    dims, nnz = ORDERS[3]
+    dims, nnz = case
     p = make(dims, (3,) * len(dims), nnz, 94)
     rng = np.random.default_rng(95)
     test = rng.random(nnz) < 0.1
@@ -87,12 +92,12 @@ def test_order8_held_out_error_and_fp32_form(prec):
     gl, ol = g.loss(), o.loss()
     # FP32: the FP32 forms' tolerance (1e-4).  At order 8 every delta is a
     # sum of 2187 FP32 column terms (order 6: 729 in the dense form), and the
-    # loss gap measured here is about 1e-5.
+    # loss gap measured there is about 1e-5.
     bar = 1e-10 if prec == "FP64" else 1e-4
-    say(prec, "order-8 loss gap %.3e" % (abs(gl["loss"] - ol["loss"]) / ol["loss"]))
+    say(prec, "order-%d loss gap %.3e" % (len(dims), abs(gl["loss"] - ol["loss"]) / ol["loss"]))
     assert abs(gl["loss"] - ol["loss"]) <= bar * ol["loss"]
     from oracle.oracle import Oracle
     ge = g.test_error(p["idx"][test], p["val"][test])
     ot = Oracle(p["idx"][test], p["val"][test], o.factors, o.core, reg=REG_LF, lam=0.05).loss()
-    say(prec, "order-8 test RE gpu %.12f oracle %.12f" % (ge["re"], ot["re"]))
+    say(prec, "order-%d test RE gpu %.12f oracle %.12f" % (len(dims), ge["re"], ot["re"]))
     assert abs(ge["sse"] - ot["sse"]) <= bar * ot["sse"]
