@@ -506,70 +506,90 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
         mbits[c] = __ballot(in && cmask[base + q] != 0);
         if (in) hdiag[base + q] = h;
     }
-    // H(q2, q) for the lane's elements q2 = lane + 64 c: the row parts of the
-    // symmetric index are fixed per lane; the reads for element q + 1 are
-    // issued before the dependent chain of element q.
-    int t2[CPL], u2[CPL];
+    // H(q2, q) for the lane's elements q2 = lane + 64 c, q = t J + u: the LDS
+    // index is a per-lane row base for (t2, t), formed once per t, plus a
+    // per-lane column offset for (u2, u), tabulated for every u; the loop over
+    // u is unrolled so that the table index is a constant.  The reads for
+    // element q + 1 are issued before the dependent chain of element q.
+    int t2[CPL], bcol[CPL][J];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int q2 = lane + c * kWave;
         t2[c] = q2 < B ? q2 / J : 0;
-        u2[c] = q2 < B ? q2 % J : 0;
+        const int u2 = q2 < B ? q2 % J : 0;
+#pragma unroll
+        for (int u = 0; u < J; ++u) bcol[c][u] = symr(J, u2, u);
     }
-    auto hcol = [&](int q, double (&hc)[CPL]) {
-        const int t = q / J, u = q % J;
+    auto rowbase = [&](int t, int (&ra)[CPL]) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) ra[c] = (J + symr(J, t2[c], t)) * GW + J;
+    };
+    auto hcol = [&](const int (&ra)[CPL], int u, int q, double (&hc)[CPL]) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int q2 = lane + c * kWave;
-            hc[c] = (q2 < B && q < B) ? sg[(J + symr(J, t2[c], t)) * GW + J + symr(J, u2[c], u)] : 0.0;
+            hc[c] = (q2 < B && q < B) ? sg[ra[c] + bcol[c][u]] : 0.0;
         }
     };
+    int ra[CPL];
+    rowbase(0, ra);
     double hcur[CPL];
-    hcol(0, hcur);
-    for (int q = 0; q < B; ++q) {
-        double hnxt[CPL];
-        hcol(q + 1, hnxt);
-        const int oc = q / kWave, ol = q % kWave;
-        uint64_t mb = mbits[0];
-        double g = gv[0], r = rv[0], h = hv[0], iq = iv[0], cc = corr[0];
+    hcol(ra, 0, 0, hcur);
+    for (int t = 0; t < J; ++t) {
+        int rn[CPL];
+        rowbase(t + 1 < J ? t + 1 : t, rn);
 #pragma unroll
-        for (int c = 1; c < CPL; ++c)
-            if (oc == c) {
-                mb = mbits[c];
-                g = gv[c];
-                r = rv[c];
-                h = hv[c];
-                iq = iv[c];
-                cc = corr[c];
-            }
-        if (!((mb >> ol) & 1ull)) {
-            g = readlane_d(g, ol);
-            r = readlane_d(r, ol);
-            h = readlane_d(h, ol);
-            iq = readlane_d(iq, ol);
-            cc = readlane_d(cc, ol);
-            // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
-            const double num = r - cc + g * h;
-            double nw;
-            if (reg == VEST_REG_LF) {
-                nw = num * iq;
-            } else {
-                const double gg = -2.0 * num;
-                nw = gg > lambda ? (lambda - gg) * iq : (gg < -lambda ? -(lambda + gg) * iq : 0.0);
-            }
-            const double dq = nw - g;
+        for (int u = 0; u < J; ++u) {
+            const int q = t * J + u;
+            double hnxt[CPL];
+            if (u + 1 < J)
+                hcol(ra, u + 1, q + 1, hnxt);
+            else
+                hcol(rn, 0, q + 1, hnxt);
+            const int oc = q / kWave, ol = q % kWave;
+            uint64_t mb = mbits[0];
+            double g = gv[0], r = rv[0], h = hv[0], iq = iv[0], cc = corr[0];
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int q2 = lane + c * kWave;
-                if (c == oc && lane == ol) {
-                    gv[c] = nw;
-                    dv[c] = dq;
+            for (int c = 1; c < CPL; ++c)
+                if (oc == c) {
+                    mb = mbits[c];
+                    g = gv[c];
+                    r = rv[c];
+                    h = hv[c];
+                    iq = iv[c];
+                    cc = corr[c];
                 }
-                corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hcur[c], dq, corr[c]) : corr[c];
+            if (!((mb >> ol) & 1ull)) {
+                g = readlane_d(g, ol);
+                r = readlane_d(r, ol);
+                h = readlane_d(h, ol);
+                iq = readlane_d(iq, ol);
+                cc = readlane_d(cc, ol);
+                // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
+                const double num = r - cc + g * h;
+                double nw;
+                if (reg == VEST_REG_LF) {
+                    nw = num * iq;
+                } else {
+                    const double gg = -2.0 * num;
+                    nw = gg > lambda ? (lambda - gg) * iq : (gg < -lambda ? -(lambda + gg) * iq : 0.0);
+                }
+                const double dq = nw - g;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int q2 = lane + c * kWave;
+                    if (c == oc && lane == ol) {
+                        gv[c] = nw;
+                        dv[c] = dq;
+                    }
+                    corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hcur[c], dq, corr[c]) : corr[c];
+                }
             }
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) hcur[c] = hnxt[c];
         }
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) hcur[c] = hnxt[c];
+        for (int c = 0; c < CPL; ++c) ra[c] = rn[c];
     }
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
