@@ -456,11 +456,11 @@ __device__ __forceinline__ double readlane_d(double v, int l)
 }
 
 // Sequential updates of one slab's unpruned elements in flat order, one
-// wave.  Lane l holds, for the elements q = l, l + 64, ..., the core value,
-// rr_q, H_qq, the reciprocal of the denominator and the running correction
-// sum_{p<q} H_qp D_p; the sequential chain reads them with readlane (no LDS
-// round trip) and only the correction update touches LDS, where H lives.  The
-// diagonal of H is kept (it is sum w_q^2, reused by the core keys).
+// wave.  Lane l holds, for the elements q = l, l + 64, ..., the running
+// correction sum_{p<q} H_qp D_p, which the sequential chain reads with
+// readlane; the element constants (core value, rr_q, H_qq, reciprocal of the
+// denominator) are LDS broadcasts, and H lives in LDS.  The diagonal of H is
+// kept (it is sum w_q^2, reused by the core keys).
 template <int J>
 __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gram, double *__restrict__ core,
                                                   const uint8_t *__restrict__ cmask, int64_t base, double lambda,
@@ -490,22 +490,31 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
     auto H = [&](int q, int q2) {
         return sg[(J + symr(J, q / J, q2 / J)) * GW + J + symr(J, q % J, q2 % J)];
     };
-    double gv[CPL], rv[CPL], hv[CPL], iv[CPL], corr[CPL], dv[CPL];
+    // per element: core value, rr, H_qq and the reciprocal of the
+    // denominator, read by every lane as LDS broadcasts; the element's new
+    // value and change, written by its owner lane when it is updated
+    __shared__ double ec[4][B], eo[2][B];
+    double corr[CPL];
     uint64_t mbits[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int q = lane + c * kWave;
         const bool in = q < B;
         const double h = in ? H(q, q) : 0.0;
-        gv[c] = in ? core[base + q] : 0.0;
-        rv[c] = in ? sg[(q / J) * GW + (q % J)] : 0.0;
-        hv[c] = h;
-        iv[c] = reg == VEST_REG_LF ? 1.0 / (h + lambda) : (h > 0.0 ? 1.0 / (2.0 * h) : 0.0);
         corr[c] = 0.0;
-        dv[c] = 0.0;
         mbits[c] = __ballot(in && cmask[base + q] != 0);
-        if (in) hdiag[base + q] = h;
+        if (in) {
+            const double g = core[base + q];
+            ec[0][q] = g;
+            ec[1][q] = sg[(q / J) * GW + (q % J)];
+            ec[2][q] = h;
+            ec[3][q] = reg == VEST_REG_LF ? 1.0 / (h + lambda) : (h > 0.0 ? 1.0 / (2.0 * h) : 0.0);
+            eo[0][q] = g;
+            eo[1][q] = 0.0;
+            hdiag[base + q] = h;
+        }
     }
+    __syncthreads();
     // H(q2, q) for the lane's elements q2 = lane + 64 c, q = t J + u: the LDS
     // index is a per-lane row base for (t2, t), formed once per t, plus a
     // per-lane column offset for (u2, u), tabulated for every u; the loop over
@@ -548,22 +557,15 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
                 hcol(rn, 0, q + 1, hnxt);
             const int oc = q / kWave, ol = q % kWave;
             uint64_t mb = mbits[0];
-            double g = gv[0], r = rv[0], h = hv[0], iq = iv[0], cc = corr[0];
+            double cc = corr[0];
 #pragma unroll
             for (int c = 1; c < CPL; ++c)
                 if (oc == c) {
                     mb = mbits[c];
-                    g = gv[c];
-                    r = rv[c];
-                    h = hv[c];
-                    iq = iv[c];
                     cc = corr[c];
                 }
             if (!((mb >> ol) & 1ull)) {
-                g = readlane_d(g, ol);
-                r = readlane_d(r, ol);
-                h = readlane_d(h, ol);
-                iq = readlane_d(iq, ol);
+                const double g = ec[0][q], r = ec[1][q], h = ec[2][q], iq = ec[3][q];
                 cc = readlane_d(cc, ol);
                 // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
                 const double num = r - cc + g * h;
@@ -575,13 +577,13 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
                     nw = gg > lambda ? (lambda - gg) * iq : (gg < -lambda ? -(lambda + gg) * iq : 0.0);
                 }
                 const double dq = nw - g;
+                if (lane == ol) {
+                    eo[0][q] = nw;
+                    eo[1][q] = dq;
+                }
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     const int q2 = lane + c * kWave;
-                    if (c == oc && lane == ol) {
-                        gv[c] = nw;
-                        dv[c] = dq;
-                    }
                     corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hcur[c], dq, corr[c]) : corr[c];
                 }
             }
@@ -591,12 +593,13 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
 #pragma unroll
         for (int c = 0; c < CPL; ++c) ra[c] = rn[c];
     }
+    __syncthreads();
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int q = lane + c * kWave;
         if (q < B) {
-            core[base + q] = gv[c];
-            dprev[q] = dv[c];
+            core[base + q] = eo[0][q];
+            dprev[q] = eo[1][q];
         }
     }
 }
