@@ -270,9 +270,10 @@ __global__ void __launch_bounds__(256) k_sel_init(SelArgs a)
 __global__ void __launch_bounds__(256) k_sel_hist(SelArgs a, int round)
 {
     __shared__ uint32_t h[kSelBins];
+    const int s = sel_segment(a, blockIdx.x);
+    if (a.krem[s] == 0) return;   // selection of this tensor already decided (k_sel_pick)
     for (int i = threadIdx.x; i < kSelBins; i += blockDim.x) h[i] = 0u;
     __syncthreads();
-    const int s = sel_segment(a, blockIdx.x);
     const SelSeg &g = a.seg[s];
     const int64_t lo = ((int64_t)blockIdx.x - g.block0) * kSelPerBlock;
     const int64_t hi = lo + kSelPerBlock < g.n ? lo + kSelPerBlock : g.n;
@@ -289,10 +290,11 @@ __global__ void __launch_bounds__(256) k_sel_hist(SelArgs a, int round)
 }
 
 // One block of 1024 threads per tensor, four bins per thread.
-__global__ void __launch_bounds__(1024) k_sel_pick(SelArgs a)
+__global__ void __launch_bounds__(1024) k_sel_pick(SelArgs a, int round)
 {
     __shared__ uint32_t part[1024];
     const int s = blockIdx.x, t = threadIdx.x;
+    if (a.krem[s] == 0) return;   // decided in an earlier round; its bins are clean
     uint32_t *gh = a.hist + (int64_t)s * kSelBins;
     uint32_t c[4];
 #pragma unroll
@@ -311,8 +313,19 @@ __global__ void __launch_bounds__(1024) k_sel_pick(SelArgs a)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (run < krem && run + c[q] >= krem) {
-            a.pref[s] = (a.pref[s] << kSelBits) | (u128)(4 * t + q);
-            a.krem[s] = krem - run;
+            const u128 p = (a.pref[s] << kSelBits) | (u128)(4 * t + q);
+            if (run + c[q] == krem) {
+                // the whole bin is selected: every composite with this prefix
+                // is at most the prefix followed by all-ones digits, and no
+                // other composite above the smaller prefixes is; the selection
+                // is decided and the later rounds are skipped
+                const int rest = kSelBits * (kSelRounds - 1 - round);
+                a.pref[s] = (p << rest) | (((u128)1 << rest) - 1);
+                a.krem[s] = 0;
+            } else {
+                a.pref[s] = p;
+                a.krem[s] = krem - run;
+            }
         }
         run += c[q];
         gh[4 * t + q] = 0u;   // clean for the next round
@@ -363,7 +376,7 @@ hipError_t launch_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
     hipLaunchKernelGGL(k_sel_init, dim3(a.nseg), dim3(256), 0, st, a);
     for (int r = 0; r < kSelRounds; ++r) {
         hipLaunchKernelGGL(k_sel_hist, dim3((unsigned)blocks), dim3(256), 0, st, a, r);
-        hipLaunchKernelGGL(k_sel_pick, dim3(a.nseg), dim3(1024), 0, st, a);
+        hipLaunchKernelGGL(k_sel_pick, dim3(a.nseg), dim3(1024), 0, st, a, r);
     }
     hipLaunchKernelGGL(k_sel_mark, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
