@@ -470,9 +470,12 @@ int vest_loss(vest_ctx *c, double *out)
     if ((rc = ensure_residual(c))) return rc;
     double *dout = c->red + 16 * kLossBlocks;
     CALL_HIP(c, launch_loss(c, dout), "loss");
-    double h[2];
-    CALL_HIP(c, hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, c->stream), "loss copy");
+    // the two sums come back through pinned host memory (a direct copy, no
+    // pageable staging), allocated on the first call, freed by vest_destroy
+    if (!c->host_red) CALL_HIP(c, hipHostMalloc((void **)&c->host_red, 64, hipHostMallocDefault), "pinned buffer");
+    CALL_HIP(c, hipMemcpyAsync(c->host_red, dout, 16, hipMemcpyDeviceToHost, c->stream), "loss copy");
     CALL_HIP(c, hipStreamSynchronize(c->stream), "loss sync");
+    const double h[2] = {c->host_red[0], c->host_red[1]};
     out[0] = h[0] + c->sse_dead;
     out[1] = c->xnorm2;
     out[2] = c->d.lambda * h[1];
@@ -670,6 +673,7 @@ int vest_destroy(vest_ctx *c)
         (void)hipEventDestroy(c->join);
     }
     if (c->slab_ev) drop_slab_events(c);
+    if (c->host_red) (void)hipHostFree(c->host_red);
     delete c;
     if (e != hipSuccess) return device_error(nullptr, e, "destroy");
     return VEST_OK;
