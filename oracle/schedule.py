@@ -11,8 +11,12 @@ Readings taken here:
     number of marks of T never exceeds ceil(s |T|) and pruning stops once the
     total sparsity reaches the target s (a lower bound on the final sparsity);
   * the automatic form stops pruning for good the first time the elbow
-    estimate (RE_t + RE_{t-2} - 2 RE_{t-1}) / pr_t exceeds 0.05; it is only
-    evaluated when RE_{t-2} exists and pr_t > 0;
+    estimate (RE_t + RE_{t-2} - 2 RE_{t-1}) / pr_t exceeds 0.05 while the RE
+    curve is rising (RE_t > RE_{t-1}): the rule is meant to find the point
+    where the RE starts to shoot up (Sec. 3.1 overview, Sec. 3.3), and the
+    convex decrease of the first iterations from a random start would
+    otherwise stop pruning at t = 3; it is only evaluated when RE_{t-2}
+    exists and pr_t > 0;
   * sparsity = (number of zero values) / (|G| + sum_n |A^(n)|)  (Sec. 4.2
     prints the complementary ratio under that name).
 """
@@ -43,8 +47,9 @@ def sparsity(arrays):
 
 
 def elbow(re_hist, pr_t):
-    """Second-difference estimate of the RE curve at the latest iteration."""
-    if len(re_hist) < 3 or pr_t <= 0:
+    """Second-difference estimate of the RE curve at the latest iteration
+    (None unless three points exist, pr_t > 0 and the curve is rising)."""
+    if len(re_hist) < 3 or pr_t <= 0 or not re_hist[-1] > re_hist[-2]:
         return None
     return (re_hist[-1] + re_hist[-3] - 2.0 * re_hist[-2]) / pr_t
 

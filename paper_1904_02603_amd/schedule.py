@@ -9,8 +9,9 @@ elements each tensor loses per prune step and when pruning stops:
     with a target sparsity s (VeST^man) the marks of a tensor never exceed
     ceil(s |T|) and pruning stops once the total sparsity reaches s;
   * VeST^auto stops pruning for good when the elbow estimate
-    (RE_t + RE_{t-2} - 2 RE_{t-1}) / pr_t exceeds 0.05 (Sec. 3.3), optionally
-    also at a sparsity cap;
+    (RE_t + RE_{t-2} - 2 RE_{t-1}) / pr_t exceeds 0.05 at a point where the RE
+    is rising (RE_t > RE_{t-1}; the elbow the rule looks for is where the RE
+    starts to shoot up, Sec. 3.1 and 3.3), optionally also at a sparsity cap;
   * sparsity = zero values / (|G| + sum_n |A^(n)|).
 """
 import math
@@ -33,7 +34,7 @@ class PruneSchedule:
 
     def elbow(self, re_hist, t):
         pr = self.rate(t)
-        if len(re_hist) < 3 or pr <= 0.0:
+        if len(re_hist) < 3 or pr <= 0.0 or not re_hist[-1] > re_hist[-2]:
             return None
         return (re_hist[-1] - 2.0 * re_hist[-2] + re_hist[-3]) / pr
 

@@ -51,3 +51,17 @@ def test_elbow_formula_value():
     assert S.elbow([0.2, 0.25, 0.4], 0.05) == pytest.approx((0.4 + 0.2 - 0.5) / 0.05)
     assert S.elbow([0.2, 0.25], 0.05) is None
     assert S.elbow([0.2, 0.25, 0.3], 0.0) is None
+
+
+def test_elbow_ignores_the_convex_decrease_of_early_iterations():
+    # from a random start the RE falls fast, then slowly: the second
+    # difference is large and positive, but the curve is not rising, so this
+    # is not the elbow where the RE shoots up (Sec. 3.1, 3.3)
+    hist = [0.9, 0.6, 0.5]
+    assert (hist[2] + hist[0] - 2 * hist[1]) / 0.03 > 0.05
+    assert S.elbow(hist, 0.03) is None
+    sched = S.AutoSchedule()
+    assert sched.should_prune(3, hist, 0.0) is True
+    # a rise that accelerates fires it
+    assert S.elbow([0.30, 0.301, 0.33], 0.05) == pytest.approx((0.33 + 0.30 - 0.602) / 0.05)
+    assert sched.should_prune(4, [0.9, 0.6, 0.5, 0.30, 0.301, 0.33], 0.1) is False
