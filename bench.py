@@ -1,17 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the VeST hot path on one MI355X.
 
-One step = one iteration of Alg. 2 on the whole workload, every step of the
-hot path included: the factor sweep of each mode (Alg. 4), the core sweep
-(Eq. 12), the loss / RE (Eq. 1, 4, one device->host read), the
-responsibility keys of every element (Eq. 5, 6) and a prune step (Sec. 3.3)
-with the VeST^man ramp pr_t = min(0.01 t, 0.1) toward 95 % sparsity.
-Inputs (indices, values, factors, core) are resident in HBM before timing.
+Headline: the dense-core workload of 10^7 observed entries over (10^5)^3,
+ranks 10^3, L_F lambda 0.01, 20 sweeps, FP64 path against the FP32 and
+split-BF16 forms, no pruning.  One step = one iteration of Alg. 2 without a
+prune step: the factor sweep of each mode (Alg. 4, Eq. 9-11), the core sweep
+(Eq. 12) and the loss / RE (Eq. 1, 4; one device->host read).  Inputs
+(indices, values, factors, core) are resident in HBM before timing.
 
 value = N * |Omega| / (seconds per step): observed-entry coordinate-descent
-updates per second, counting one update per entry and mode of the factor
-sweeps (the core sweep, loss, keys and prune are inside the timed step but
-not counted as updates).
+updates per second, one update per entry and mode of the factor sweeps (the
+core sweep and the loss are inside the timed step but not counted).
+
+Labelled sections beside the headline:
+  * prune_step: the responsibility keys (Eq. 5, 6) and one prune step
+    (Sec. 3.3) on the state the FP64 leg reached, timed per call;
+  * prune_ramp: the three forms from the same start through the VeST^man
+    ramp pr_t = min(0.01 t, 0.1) toward 95 % sparsity, in lockstep, with the
+    prune masks of the FP32 / BF16 forms compared with the FP64 ones after
+    every prune step (differing elements and their key gaps) and the RE gap;
+  * pruned_phase: factor sweeps with 95 % of every tensor marked (dense and
+    gather contraction, and after compaction);
+  * serving: the request loop over a Poisson stream of jobs.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -42,23 +52,66 @@ def sweep_flops_per_entry(N, J):
     return 2 * sum(J ** m for m in range(2, N + 1)) + J * (J + 1) + 2 * J
 
 
-def slab_bytes_per_launch(N, J, nnz, dims, ts):
-    """Algorithmic HBM bytes of one timed slab pass of the core sweep (passes 2
+def slab_alg_bytes_per_launch(N, J, nnz, dims, ts):
+    """Algorithmic HBM bytes of one slab pass of the core sweep, by the count
+    of the method: per observed entry its N int32 indices and the residual
+    read and written (4 N + 2 s_val bytes); once per pass the factor matrices
+    the pass reads (the last two modes' rows, one column of each leading
+    mode).  Gathered factor rows are counted once per matrix."""
+    per_entry = 4 * N + 2 * ts
+    once = (dims[N - 2] + dims[N - 1]) * J * 8 + sum(d * 8 for d in dims[:N - 2])
+    return nnz * per_entry + once
+
+
+def slab_design_bytes_per_launch(N, J, nnz, dims, ts):
+    """Bytes one slab pass of this implementation streams by design (passes 2
     to J^(N-2); the first slab's statistics come from the residual pass): per
     entry the residual read and written, the slot copy of the mode N-2 row (J
     values) and the N-2 leading indices; once per pass the per-row statistics
     of the last mode (J + J(J+1)/2 FP64 values), that mode's factor rows and
-    the two leading-factor columns."""
+    the leading-factor columns."""
     per_entry = 2 * ts + J * ts + 4 * (N - 2)
     rows = dims[N - 1]
     once = rows * (J + J * (J + 1) // 2) * 8 + rows * J * ts + sum(2 * d * ts for d in dims[:N - 2])
     return nnz * per_entry + once
 
 
-def run_leg(p, precision, steps, warmup, target):
+def sweep_alg_bytes(N, nnz, dims, J, ts):
+    """Algorithmic HBM bytes of one factor sweep (one mode): the streamed
+    entries ((N-1) int32 indices + one value) plus every factor matrix once
+    (the swept one read and written, the others read); averaged over modes."""
+    return nnz * ((N - 1) * 4 + ts) + sum(d * J * 8 for d in dims) * (N + 1) / N
+
+
+class EventLog:
+    """HIP events around library calls on the context's stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.ev = {}
+
+    def timed(self, name, fn, rec=True):
+        import torch
+        if not rec:
+            return fn()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        out = fn()
+        b.record(self.stream)
+        self.ev.setdefault(name, []).append((a, b))
+        return out
+
+    def ms(self):
+        return {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in self.ev.items() if v}
+
+
+def dense_leg(p, precision, steps, warmup):
+    """The headline leg of one form: `warmup` untimed and `steps` timed
+    iterations (factor sweeps of every mode, core sweep, loss), no pruning.
+    Returns the timings and the context, left open at its final state."""
     import torch
     from paper_1904_02603_amd import vest
-    from paper_1904_02603_amd.schedule import PruneSchedule
 
     N = p["idx"].shape[1]
     nnz = p["idx"].shape[0]
@@ -68,95 +121,170 @@ def run_leg(p, precision, steps, warmup, target):
                            precision=precision)
     torch.cuda.synchronize()
     log("  init (layout build) %.2f s, workspace %.2f GB" % (time.perf_counter() - t0, ctx.ws_bytes / 1e9))
-    stream = torch.cuda.current_stream()
-    sched = PruneSchedule(mode="manual", target=target)
-    sizes = [f.numel() for f in ctx.factors]
-    marked = {"core": 0, "fac": [0] * N}
-    names = ["sweep_factor_%d" % n for n in range(N)] + ["sweep_core", "loss", "responsibility", "prune"]
-    events = {k: [] for k in names}
+    log_ = EventLog(torch.cuda.current_stream())
 
-    def timed(name, fn, rec):
-        if rec:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            out = fn()
-            b.record(stream)
-            events[name].append((a, b))
-            return out
-        return fn()
-
-    def step(t, rec):
+    def step(rec):
         for n in range(N):
-            timed("sweep_factor_%d" % n, lambda: ctx.sweep_factor(n), rec)
-        timed("sweep_core", ctx.sweep_core, rec)
-        L = timed("loss", ctx.loss, rec)
-        timed("responsibility", ctx.responsibility, rec)
-        ck = sched.count(t, ctx.core.numel(), marked["core"])
-        fk = [sched.count(t, s, m) for s, m in zip(sizes, marked["fac"])]
-        timed("prune", lambda: ctx.prune(ck, fk), rec)
-        marked["core"] += ck
-        marked["fac"] = [m + k for m, k in zip(marked["fac"], fk)]
-        return L
+            log_.timed("sweep_factor_%d" % n, lambda: ctx.sweep_factor(n), rec)
+        log_.timed("sweep_core", ctx.sweep_core, rec)
+        return log_.timed("loss", ctx.loss, rec)
 
-    t = 0
     for _ in range(warmup):
-        t += 1
-        step(t, False)
+        step(False)
     ctx.slab_timing(True)   # events around every slab pass of the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    re = None
+    L = None
     for _ in range(steps):
-        t += 1
-        re = step(t, True)["re"]
+        L = step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     slab_total, slab_n = ctx.slab_time()
     ctx.slab_timing(False)
-    ms = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in events.items() if v}
+    ms = log_.ms()
     ms_step = elapsed * 1e3 / steps
     J = ctx.J
-    fl = sweep_flops_per_entry(N, J) * nnz
     sweep_ms = sum(ms["sweep_factor_%d" % n] for n in range(N)) / N
     dims = [int(f.shape[0]) for f in ctx.factors]
     ts = 8 if precision == vest.FP64 else 4
-    ctx.close()
-    return {
+    return ctx, {
         "slab_kernel_ms": slab_total / max(1, slab_n),
         "slab_launches": slab_n,
-        "slab_bytes_per_launch": slab_bytes_per_launch(N, J, nnz, dims, ts),
+        "slab_alg_bytes_per_launch": slab_alg_bytes_per_launch(N, J, nnz, dims, ts),
+        "slab_design_bytes_per_launch": slab_design_bytes_per_launch(N, J, nnz, dims, ts),
         "ms_per_step": ms_step,
         "value": N * nnz / (ms_step / 1e3),
         "sweep_only_value": N * nnz / (sweep_ms * N / 1e3),
+        "full_sweep_value": nnz / ((sweep_ms * N + ms["sweep_core"]) / 1e3),
+        "core_value": nnz * ctx.core.numel() / (ms["sweep_core"] / 1e3),
         "breakdown_ms": {k: round(v, 4) for k, v in ms.items()},
         "sweep_kernel_ms": sweep_ms,
-        "sweep_flops_per_launch": fl,
-        "final_re": re,
+        "sweep_flops_per_launch": sweep_flops_per_entry(N, J) * nnz,
+        "sweep_alg_bytes": sweep_alg_bytes(N, nnz, dims, J, ts),
+        "final_re": L["re"],
+        "final_loss": L["loss"],
     }
 
 
-def dense_accuracy(p, iters):
-    """RE and factor error of the FP32 / BF16 forms against the FP64 path after
-    `iters` full iterations without pruning (same start, same masks)."""
+def compare_states(ctx, ref):
+    """Relative RE gap and factor / core errors of a context against the FP64
+    leg's final state (same start, same number of iterations)."""
+    import torch
+    L = ctx.loss()
+    out = {"re": L["re"], "re_gap_vs_fp64": abs(L["re"] - ref["re"]) / ref["re"]}
+    errs, rms = [], []
+    for a, b in zip(list(ctx.factors) + [ctx.core], ref["tensors"]):
+        d = (a - b).abs()
+        errs.append(float(d.max() / b.abs().max()))
+        rms.append(float(torch.sqrt((d * d).mean()) / torch.sqrt((b * b).mean())))
+    out["factor_rel_err_max"] = max(errs[:-1])
+    out["core_rel_err_max"] = errs[-1]
+    out["rel_rmse_factors"] = max(rms[:-1])
+    out["rel_rmse_core"] = rms[-1]
+    return out
+
+
+def prune_step_section(ctx, reps=1):
+    """Responsibility keys (Eq. 5, 6) and one prune step (Sec. 3.3, first
+    ramp step pr_1 = 0.01) on a context's current state, per-call times."""
+    import torch
+    from paper_1904_02603_amd.schedule import PruneSchedule
+    lg = EventLog(torch.cuda.current_stream())
+    for _ in range(reps):
+        lg.timed("responsibility", ctx.responsibility)
+    sched = PruneSchedule(mode="manual", target=0.95)
+    ck = sched.count(1, ctx.core.numel(), 0)
+    fk = [sched.count(1, f.numel(), 0) for f in ctx.factors]
+    lg.timed("prune", lambda: ctx.prune(ck, fk))
+    torch.cuda.synchronize()
+    ms = lg.ms()
+    return {"responsibility_ms": ms["responsibility"], "prune_ms": ms["prune"], "responsibility_calls": reps,
+            "pruned": {"core": ck, "factors": fk}}
+
+
+def mask_differences(ref_ctx, ref_keys, new_ref, ctx, new):
+    """A23 report for one prune step: elements whose prune decision differs
+    between a reduced-precision form and the FP64 path, and the gap of their
+    FP64 keys to the FP64 selection threshold (largest selected key) relative
+    to that threshold's magnitude."""
+    import torch
+    diff, gaps = 0, []
+    for rk, rnew, nnew in zip(ref_keys, new_ref, new):
+        d = rnew ^ nnew
+        n = int(d.sum())
+        diff += n
+        if n and bool(rnew.any()):
+            thr = rk[rnew].max()
+            g = ((rk[d] - thr).abs() / thr.abs().clamp_min(1e-300))
+            g = g[torch.isfinite(g)]
+            if g.numel():
+                gaps.append(float(g.max()))
+    return diff, (max(gaps) if gaps else None)
+
+
+def prune_ramp_section(p, iters, target):
+    """The three forms from the same start through the VeST^man ramp, in
+    lockstep: iteration, loss, responsibility, prune (counts from the shared
+    schedule).  Reports time per step of every form, the RE gap of FP32 /
+    BF16 against FP64 after the ramp, and per prune step the number of
+    elements whose prune decision differs from FP64's and their key gaps."""
     import torch
     from paper_1904_02603_amd import vest
-    out, ref = {}, None
-    for name, prec in [("fp64", vest.FP64), ("fp32", vest.FP32), ("bf16", vest.BF16)]:
-        ctx = vest.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"],
-                               precision=prec)
-        for _ in range(iters):
-            ctx.iteration()
-        L = ctx.loss()
-        fac = [f.double().cpu() for f in ctx.factors]
-        ctx.close()
-        if ref is None:
-            ref = (L["re"], fac)
-            out["fp64_re"] = L["re"]
-            continue
-        err = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(fac, ref[1]))
-        out[name] = {"re": L["re"], "re_gap_vs_fp64": abs(L["re"] - ref[0]) / ref[0], "factor_rel_err": err}
-    out["iterations"] = iters
+    from paper_1904_02603_amd.schedule import PruneSchedule
+    forms = [("fp64", vest.FP64), ("fp32", vest.FP32), ("bf16", vest.BF16)]
+    ctxs = {n: vest.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"],
+                                precision=f) for n, f in forms}
+    N = p["idx"].shape[1]
+    sched = PruneSchedule(mode="manual", target=target)
+    sizes = [f.size for f in p["factors"]]
+    csize = p["core"].size
+    mc, mf = 0, [0] * N
+    logs = {n: EventLog(torch.cuda.current_stream()) for n, _ in forms}
+    steps = []
+    for t in range(1, iters + 1):
+        ck = sched.count(t, csize, mc)
+        fk = [sched.count(t, s, m) for s, m in zip(sizes, mf)]
+        rec = {"t": t, "pruned": ck + sum(fk)}
+        before = {}
+        for name, _ in forms:
+            c = ctxs[name]
+            before[name] = [m.clone() for m in c.factor_masks_bool()] + [c.cmask.bool().clone()]
+
+            def one(c=c):
+                c.iteration()
+                L = c.loss()
+                c.responsibility()
+                c.prune(ck, fk)
+                return L
+            L = logs[name].timed("step", one)
+            rec[name + "_re"] = L["re"]
+        torch.cuda.synchronize()
+        new = {}
+        for name, _ in forms:
+            c = ctxs[name]
+            after = [m for m in c.factor_masks_bool()] + [c.cmask.bool()]
+            new[name] = [a & ~b for a, b in zip(after, before[name])]
+        refk = list(ctxs["fp64"].factor_keys) + [ctxs["fp64"].core_key]
+        for name in ("fp32", "bf16"):
+            d, g = mask_differences(ctxs["fp64"], refk, new["fp64"], ctxs[name], new[name])
+            rec[name + "_mask_diff"] = d
+            rec[name + "_max_key_gap"] = g
+        mc += ck
+        mf = [m + k for m, k in zip(mf, fk)]
+        steps.append(rec)
+    out = {"iterations": iters, "target": target, "steps": steps,
+           "marked_fraction": (mc + sum(mf)) / (csize + sum(sizes))}
+    L64 = ctxs["fp64"].loss()
+    for name, _ in forms:
+        out[name + "_ms_per_step"] = logs[name].ms()["step"]
+        if name != "fp64":
+            L = ctxs[name].loss()
+            out[name + "_re_gap_vs_fp64"] = abs(L["re"] - L64["re"]) / L64["re"]
+            out[name + "_first_divergent_step"] = next(
+                (s["t"] for s in steps if s[name + "_mask_diff"]), None)
+    out["fp64_final_re"] = L64["re"]
+    for c in ctxs.values():
+        c.close()
     return out
 
 
@@ -397,7 +525,16 @@ def cpu_baseline(p, seconds):
             k += 1
         spent += time.perf_counter() - t0
         rows += k
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": entries / spent, "unit": "entry-updates/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_nproc": os.cpu_count(), "host_affinity": len(os.sched_getaffinity(0)),
             "sample": "single-threaded FP64 oracle, Alg. 4 row updates of %d randomly chosen rows "
                       "(%d observed entries, all modes) of the same workload, %.1f s" % (rows, entries, spent)}
 
@@ -405,13 +542,15 @@ def cpu_baseline(p, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--nnz", type=int, default=None, help="smaller nnz for a quick run (not a bench line)")
     ap.add_argument("--target", type=float, default=0.95)
-    ap.add_argument("--no-fp32", action="store_true", help="FP64 leg only (no FP32 / BF16 legs)")
-    ap.add_argument("--accuracy-iters", type=int, default=5)
+    ap.add_argument("--legs", default="fp64,fp32,bf16",
+                    help="comma list of forms to time (the first must be fp64 for a bench line)")
+    ap.add_argument("--ramp-iters", type=int, default=16,
+                    help="iterations of the prune-ramp section (0 = skip it)")
     ap.add_argument("--sparse-frac", type=float, default=0.95,
                     help="marked fraction of the pruned-phase sweep section (0 = skip it)")
     ap.add_argument("--serve-jobs", type=int, default=512, help="serving stream length (0 = skip)")
@@ -419,8 +558,6 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-arena-gb", type=float, default=32.0)
     ap.add_argument("--serve-calib", type=int, default=32)
-    ap.add_argument("--legs", default="fp64,fp32,bf16",
-                    help="comma list of forms to time (the first must be fp64 for a bench line)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counters)")
@@ -455,35 +592,48 @@ def main():
     N, nnz = p["idx"].shape[1], p["idx"].shape[0]
     J = p["factors"][0].shape[1]
     log("  %.1f s: dims %s, nnz %d, ranks %d" % (time.perf_counter() - t0, [f.shape[0] for f in p["factors"]], nnz, J))
-
+    forms = {"fp64": vest.FP64, "fp32": vest.FP32, "bf16": vest.BF16}
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
-    if args.no_fp32:
-        legs = ["fp64"]
-    if "fp64" not in legs:
+    if legs[0] != "fp64":
         # profiling runs of one low-precision form: time it, print nothing else
         for name in legs:
-            r = run_leg(p, {"fp32": vest.FP32, "bf16": vest.BF16}[name], args.steps, args.warmup, args.target)
+            ctx, r = dense_leg(p, forms[name], args.steps, args.warmup)
+            ctx.close()
             log("%s: %.3f ms/step, sweep kernel %.3f ms" % (name, r["ms_per_step"], r["sweep_kernel_ms"]))
         return
-    log("FP64 leg ...")
-    f64 = run_leg(p, vest.FP64, args.steps, args.warmup, args.target)
-    log("  %.3f ms/step, sweep kernel %.3f ms" % (f64["ms_per_step"], f64["sweep_kernel_ms"]))
+
+    log("FP64 leg (%d + %d dense iterations) ..." % (args.warmup, args.steps))
+    ctx64, f64 = dense_leg(p, vest.FP64, args.steps, args.warmup)
+    log("  %.3f ms/step, sweep kernel %.3f ms, slab pass %.3f ms" % (
+        f64["ms_per_step"], f64["sweep_kernel_ms"], f64["slab_kernel_ms"]))
+    ref = {"re": f64["final_re"], "tensors": [f.clone() for f in ctx64.factors] + [ctx64.core.clone()]}
+    log("prune step section (responsibility + one prune step on the FP64 state) ...")
+    prune_step = prune_step_section(ctx64)
+    ctx64.close()
+    del ctx64
     lowp = {}
-    acc = None
-    if len(legs) > 1:
-        for name, prec in [(n, {"fp32": vest.FP32, "bf16": vest.BF16}[n]) for n in legs if n != "fp64"]:
-            log("%s leg ..." % name.upper())
-            lowp[name] = run_leg(p, prec, args.steps, args.warmup, args.target)
-            log("  %.3f ms/step, sweep kernel %.3f ms" % (lowp[name]["ms_per_step"], lowp[name]["sweep_kernel_ms"]))
-        if args.accuracy_iters > 0:
-            log("dense-phase accuracy (%d iterations, no pruning) ..." % args.accuracy_iters)
-            acc = dense_accuracy(p, args.accuracy_iters)
+    for name in legs[1:]:
+        log("%s leg ..." % name.upper())
+        ctx, r = dense_leg(p, forms[name], args.steps, args.warmup)
+        r["vs_fp64"] = compare_states(ctx, ref)
+        ctx.close()
+        lowp[name] = r
+        log("  %.3f ms/step, sweep kernel %.3f ms; RE gap vs FP64 %.2e" % (
+            r["ms_per_step"], r["sweep_kernel_ms"], r["vs_fp64"]["re_gap_vs_fp64"]))
+    del ref
+    torch.cuda.empty_cache()
+    ramp = None
+    if args.ramp_iters > 0 and len(legs) == 3:
+        log("prune ramp (%d iterations, three forms in lockstep) ..." % args.ramp_iters)
+        ramp = prune_ramp_section(p, args.ramp_iters, args.target)
+        log("  FP64 %.3f ms/step; RE gap FP32 %.2e, BF16 %.2e; first differing masks FP32 t=%s, BF16 t=%s" % (
+            ramp["fp64_ms_per_step"], ramp["fp32_re_gap_vs_fp64"], ramp["bf16_re_gap_vs_fp64"],
+            ramp["fp32_first_divergent_step"], ramp["bf16_first_divergent_step"]))
     sparse = {}
     if args.sparse_frac > 0:
         for name in legs:
             log("pruned-phase sweeps (%s, %.0f %% marked) ..." % (name, 100 * args.sparse_frac))
-            sparse[name] = sparse_phase(p, args.sparse_frac, args.steps,
-                                        {"fp64": vest.FP64, "fp32": vest.FP32, "bf16": vest.BF16}[name])
+            sparse[name] = sparse_phase(p, args.sparse_frac, min(args.steps, 10), forms[name])
             log("  dense %.3f ms, gather %.3f ms per sweep; compacted to %d entries in %.2f s: %.3f ms" % (
                 sparse[name]["dense_ms_per_sweep"], sparse[name]["gather_ms_per_sweep"],
                 sparse[name]["live_entries"], sparse[name]["compaction_s"], sparse[name]["compacted_ms_per_sweep"]))
@@ -499,9 +649,11 @@ def main():
         log("oracle CPU baseline ...")
         cpu = cpu_baseline(p, args.cpu_seconds)
 
-    achieved = f64["sweep_flops_per_launch"] / (f64["sweep_kernel_ms"] / 1e3) / 1e12
-    slab_gbs = f64["slab_bytes_per_launch"] / (f64["slab_kernel_ms"] / 1e3) / 1e9
     named = args.workload == DEFAULT_WORKLOAD and args.nnz is None
+    slab_gbs = f64["slab_alg_bytes_per_launch"] / (f64["slab_kernel_ms"] / 1e3) / 1e9
+    sweep_tf = f64["sweep_flops_per_launch"] / (f64["sweep_kernel_ms"] / 1e3) / 1e12
+    slab_share = f64["slab_kernel_ms"] * f64["slab_launches"] / args.steps / f64["ms_per_step"]
+    sweep_share = f64["sweep_kernel_ms"] * N / f64["ms_per_step"]
     out = {
         "metric": METRIC,
         "value": f64["value"],
@@ -517,35 +669,43 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": [int(f.shape[0]) for f in p["factors"]], "nnz": nnz,
                    "ranks": [J] * N, "reg": "L_F" if p["reg"] == 0 else "L_1", "lambda": p["lam"],
-                   "step": "factor sweeps (all modes) + core sweep + loss + responsibility + prune",
-                   "prune": "manual ramp min(0.01 t, 0.1) toward %.2f" % args.target},
-        # the kernel with the largest share of the step: J^(N-2) slab passes per core sweep
+                   "core": "dense", "sweeps_timed": args.steps,
+                   "step": "factor sweeps (all modes) + core sweep + loss; no pruning",
+                   "forms": "FP64 (value) vs FP32 / split-BF16 (keys fp32, bf16)"},
+        # the kernel with the largest share of the step: the slab passes of the core sweep
         "roofline": {"kernel": "k_slab (slab pass of the core sweep)", "bound": "hbm",
                      "achieved": slab_gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": slab_gbs / HBM_PEAK,
                      "traffic": measured_traffic("slab") if named else None,
-                     "bytes_per_launch": f64["slab_bytes_per_launch"],
-                     "avg_launch_ms": f64["slab_kernel_ms"], "launches_timed": f64["slab_launches"]},
-        "roofline_sweep": {"kernel": "k_rowgroup<OP_SWEEP> (factor sweep, one mode)", "bound": "alu",
-                           "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
-                           "frac": achieved / PEAK["f64"],
+                     "algorithmic_bytes_per_launch": f64["slab_alg_bytes_per_launch"],
+                     "design_bytes_per_launch": f64["slab_design_bytes_per_launch"],
+                     "avg_launch_ms": f64["slab_kernel_ms"], "launches_timed": f64["slab_launches"],
+                     "share_of_step": slab_share},
+        "roofline_sweep": {"kernel": "k_rowgroup<OP_SWEEP> dense contraction (factor sweep, one mode)",
+                           "bound": "alu", "achieved": sweep_tf, "peak": PEAK["f64"], "unit": "TFLOP/s",
+                           "frac": sweep_tf / PEAK["f64"],
                            "traffic": measured_traffic("sweep") if named else None,
+                           "algorithmic_bytes_per_launch": f64["sweep_alg_bytes"],
                            "flops_per_launch": f64["sweep_flops_per_launch"],
-                           "avg_launch_ms": f64["sweep_kernel_ms"]},
+                           "avg_launch_ms": f64["sweep_kernel_ms"], "share_of_step": sweep_share},
         "cpu_baseline": cpu,
         "breakdown_ms": f64["breakdown_ms"],
         "sweep_only_value": f64["sweep_only_value"],
+        "full_sweep_value": f64["full_sweep_value"],
+        "core_value": f64["core_value"],
         "final_re": f64["final_re"],
+        "prune_step": prune_step,
     }
+    out["prune_step"]["step_with_prune_ms"] = (f64["ms_per_step"] + prune_step["responsibility_ms"]
+                                               + prune_step["prune_ms"])
     for name, r in lowp.items():
-        out[name] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+        out[name] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "speedup_vs_fp64": r["value"] / f64["value"],
                      "sweep_only_value": r["sweep_only_value"], "breakdown_ms": r["breakdown_ms"],
                      "sweep_tflops": r["sweep_flops_per_launch"] / (r["sweep_kernel_ms"] / 1e3) / 1e12,
                      "slab_pass_ms": r["slab_kernel_ms"],
-                     "slab_pass_gbs": r["slab_bytes_per_launch"] / (r["slab_kernel_ms"] / 1e3) / 1e9,
-                     "final_re": r["final_re"],
-                     "re_gap_vs_fp64_pruned": abs(r["final_re"] - f64["final_re"]) / f64["final_re"]}
-    if acc is not None:
-        out["accuracy_dense"] = acc
+                     "slab_pass_alg_gbs": r["slab_alg_bytes_per_launch"] / (r["slab_kernel_ms"] / 1e3) / 1e9,
+                     "accuracy_vs_fp64": r["vs_fp64"]}
+    if ramp is not None:
+        out["prune_ramp"] = ramp
     if sparse:
         out["pruned_phase"] = sparse
     if serving is not None:
