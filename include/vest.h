@@ -173,6 +173,33 @@ int vest_export(vest_ctx *ctx, int64_t *const *fac_idx, double *const *fac_val, 
  * VEST_EINVAL for an index out of range.  Synchronises the stream. */
 int vest_test_error(vest_ctx *ctx, const int32_t *idx, const double *val, int64_t n, double *out);
 
+/* Allocation-free variant of vest_test_error, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops or
+ * harnesses that forbid hipMalloc): the same loss terms of a model given as
+ * plain device arrays, with no context and no workspace.
+ *   desc       host; order, dims and ranks are read (ranks may differ per
+ *              mode); nnz, reg, lambda and precision are ignored
+ *   stream     hipStream_t the kernels are enqueued on (NULL = default)
+ *   factors    host array of N device pointers, A_n row-major I_n x J_n FP64
+ *   core       prod(J_n) FP64, flat order
+ *   idx, val   n*N int32 entry-major and n FP64, device
+ *   out        DEVICE, 4 doubles: sum (X - B)^2, sum X^2, RE, and the number
+ *              of entries with an index out of range (the first three are
+ *              NaN when it is not 0)
+ * Only enqueues (two kernels, no copy, no synchronisation, no allocation by
+ * the library or the runtime).  Per-block partial sums live in a static
+ * device array of the library, 3 * 8 bytes per 1024 entries, so n is limited
+ * to VEST_NOALLOC_MAX_ENTRIES (VEST_EINVAL beyond, before anything is
+ * enqueued).  Each GPU has one such array, kept until the process ends and
+ * shared by every call on that GPU: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.  Every
+ * call writes each partial it reads, so no clearing is needed.  Returns
+ * VEST_EINVAL for a bad argument and VEST_EDEVICE for a launch error. */
+#define VEST_NOALLOC_MAX_ENTRIES (1 << 24)
+int vest_model_error_noalloc(const vest_desc *desc, void *stream, const double *const *factors,
+                             const double *core, const int32_t *idx, const double *val, int64_t n,
+                             double *out);
+
 /* Keys of the value-pruning comparator: |value| of every unmarked element,
  * +infinity for marked ones, written like vest_responsibility's keys and
  * made the pending keys of the next vest_prune (which then removes the

@@ -24,7 +24,7 @@ EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep
            "vest_responsibility", "vest_prune", "vest_loss", "vest_normalize", "vest_count_nonzeros",
            "vest_export", "vest_test_error", "vest_value_keys", "vest_compact", "vest_set_kernel",
            "vest_layout_stats", "vest_slab_timing", "vest_slab_time", "vest_destroy", "vest_strerror",
-           "vest_last_error",
+           "vest_last_error", "vest_model_error_noalloc",
            "vest_server_create", "vest_server_submit", "vest_server_progress", "vest_server_status",
            "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -75,6 +75,7 @@ def load_library(path=LIB_PATH):
     lib.vest_count_nonzeros.argtypes = [vp, vp]
     lib.vest_export.argtypes = [vp, vp, vp, vp, vp]
     lib.vest_test_error.argtypes = [vp, vp, vp, i64, vp]
+    lib.vest_model_error_noalloc.argtypes = [PD, vp, vp, vp, vp, vp, i64, vp]
     lib.vest_value_keys.argtypes = [vp, vp, vp]
     lib.vest_layout_stats.argtypes = [vp, i32, vp]
     lib.vest_slab_timing.argtypes = [vp, i32]
@@ -97,7 +98,7 @@ def load_library(path=LIB_PATH):
     for name in ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
                  "vest_responsibility", "vest_prune", "vest_loss", "vest_normalize", "vest_count_nonzeros",
                  "vest_export", "vest_test_error", "vest_value_keys", "vest_compact", "vest_set_kernel",
-                 "vest_layout_stats", "vest_destroy"]:
+                 "vest_layout_stats", "vest_destroy", "vest_model_error_noalloc"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -304,6 +305,24 @@ class VestContext:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_MAX_ENTRIES = 1 << 24
+
+
+def model_error_noalloc(factors, core, idx, val, out, stream=None):
+    """vest_model_error_noalloc: held-out loss terms of a model given as device
+    tensors (factors: list of float64 [I_n, J_n], core float64), entries idx
+    int32 [n, N] and val float64 [n] on the device; out is a float64 device
+    tensor of 4 values, written on `stream` (no synchronisation)."""
+    lib = load_library()
+    dims = [int(f.shape[0]) for f in factors]
+    ranks = [int(f.shape[1]) for f in factors]
+    desc = make_desc(dims, ranks, max(1, int(idx.shape[0])))
+    st = stream if stream is not None else torch.cuda.current_stream(out.device)
+    _check(lib.vest_model_error_noalloc(C.byref(desc), C.c_void_p(st.cuda_stream), _ptr_array(factors), _ptr(core),
+                                        _ptr(idx), _ptr(val), int(idx.shape[0]), _ptr(out)),
+           "vest_model_error_noalloc")
 
 
 def job_footprint(dims, ranks, nnz, reg=REG_LF, lam=0.01, precision=FP32):
