@@ -30,6 +30,11 @@
  *     ||X||^2 (RE(e)^2 - RE^2) and orders exactly like Resp(e) of Eq. 3 when
  *     RE > 0; ties are broken by ascending flat index.  The core step of
  *     Alg. 3 omits the square; Eq. 5 is used.
+ *   - The paper fixes no summation order.  Every sum of this file (delta and
+ *     B over the core elements, the row and core statistics over entries, the
+ *     loss) is Neumaier-compensated, so that its result is close to the
+ *     correctly rounded one whatever the order; the FP64 comparison with the
+ *     GPU is then a comparison with (nearly) the exact value.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -37,6 +42,7 @@
 #include <math.h>
 
 #define OR_MAX_ORDER 10
+#define OR_MAX_RANK 64                 /* row_stats holds a delta of this length */
 
 typedef struct {
     int32_t order;                    /* N */
@@ -128,7 +134,8 @@ void or_delta(const or_state *st, int32_t n, int64_t e, double *delta)
     int32_t j[OR_MAX_ORDER];
     const int32_t *a = st->idx + e * st->order;
     int64_t G = core_size(st);
-    for (int32_t t = 0; t < st->ranks[n]; ++t) delta[t] = 0.0;
+    ksum acc[OR_MAX_RANK];
+    for (int32_t t = 0; t < st->ranks[n]; ++t) acc[t].s = acc[t].c = 0.0;
     for (int64_t beta = 0; beta < G; ++beta) {
         unflatten(st, beta, j);
         double p = st->core[beta];
@@ -136,8 +143,9 @@ void or_delta(const or_state *st, int32_t n, int64_t e, double *delta)
             if (k == n) continue;
             p *= st->factors[k][(int64_t)a[k] * st->ranks[k] + j[k]];
         }
-        delta[j[n]] += p;
+        ks_add(&acc[j[n]], p);
     }
+    for (int32_t t = 0; t < st->ranks[n]; ++t) delta[t] = ks_val(&acc[t]);
 }
 
 /* ---------------- Eq. 7: entry-wise reconstruction B(alpha) -------------- */
@@ -146,15 +154,15 @@ double or_recon(const or_state *st, int64_t e)
     int32_t j[OR_MAX_ORDER];
     const int32_t *a = st->idx + e * st->order;
     int64_t G = core_size(st);
-    double b = 0.0;
+    ksum b = {0, 0};
     for (int64_t beta = 0; beta < G; ++beta) {
         unflatten(st, beta, j);
         double p = st->core[beta];
         for (int k = 0; k < st->order; ++k)
             p *= st->factors[k][(int64_t)a[k] * st->ranks[k] + j[k]];
-        b += p;
+        ks_add(&b, p);
     }
-    return b;
+    return ks_val(&b);
 }
 
 /* Residuals X_alpha - B(alpha) for every observed entry (first step of Alg. 3). */
