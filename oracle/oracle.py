@@ -17,20 +17,24 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vest_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 MAX_ORDER = 10
 
 REG_LF = 0
 REG_L1 = 1
 
 
-def build(force=False):
-    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force=False, omp=False):
+    """Compile the oracle with gcc (no FMA contraction, no fast-math).
+    omp=True builds the optional OpenMP variant (liboracle_omp.so), which
+    splits only independent sums and returns the same bits."""
+    lib = _LIB_OMP if omp else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math"]
+                              + (["-fopenmp"] if omp else []) + ["-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _State(C.Structure):
@@ -58,7 +62,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        lib = C.CDLL(build())
+        lib = C.CDLL(build(omp=os.environ.get("VEST_ORACLE_OMP") == "1"))
         P = C.POINTER(_State)
         vp = C.c_void_p
         lib.or_build_rows.argtypes = [P]

@@ -6,7 +6,10 @@
  * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the benchmark's
  * CPU-baseline leg may load this library.  It shares no code, header, table or
  * helper with the GPU library; the two meet only through the seeded synthetic
- * inputs.  Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math.
+ * inputs.  Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math.  An
+ * optional OpenMP build of the same source (-fopenmp) splits only loops whose
+ * iterations are independent sums (factor rows, residual entries, keys), so
+ * it returns the same bits; the sequential core update stays sequential.
  *
  * Conventions (all 0-based):
  *   idx[e*N + n]        mode-n index of observed entry e (canonical entry id e)
@@ -168,6 +171,7 @@ double or_recon(const or_state *st, int64_t e)
 /* Residuals X_alpha - B(alpha) for every observed entry (first step of Alg. 3). */
 void or_residual(const or_state *st, double *res)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < st->nnz; ++e) res[e] = st->val[e] - or_recon(st, e);
 }
 
@@ -248,6 +252,9 @@ void or_update_factor_elem(or_state *st, int32_t n, int64_t i, int32_t j)
 /* One pass of Alg. 4 over all rows of mode n. */
 void or_sweep_factor(or_state *st, int32_t n)
 {
+    /* rows are independent (each reads the other modes and writes its own
+       row), so the optional OpenMP build gives the same bits */
+#pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < st->dims[n]; ++i) or_update_row(st, n, i);
 }
 
@@ -277,8 +284,10 @@ static void core_coord(or_state *st, int64_t beta, double *res)
     }
     double gn = coord_min(st->reg, st->lambda, ks_val(&num), ks_val(&den));
     double dg = gn - g;
-    if (dg != 0.0)
+    if (dg != 0.0) {
+#pragma omp parallel for schedule(static)
         for (int64_t e = 0; e < st->nnz; ++e) res[e] -= dg * core_weight(st, e, j);
+    }
     st->core[beta] = gn;
 }
 
@@ -342,12 +351,14 @@ void or_loss(const or_state *st, double *out)
  * Pruned elements get +infinity so that they are never selected again. */
 void or_responsibility(const or_state *st, double *core_key, double **factor_key)
 {
-    int32_t j[OR_MAX_ORDER];
-    double delta[64];
     double *res = (double *)malloc((size_t)(st->nnz > 0 ? st->nnz : 1) * sizeof(double));
     or_residual(st, res);
     int64_t G = core_size(st);
+    /* every key is its own sum from the same snapshot: the optional OpenMP
+       build gives the same bits */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t beta = 0; beta < G; ++beta) {
+        int32_t j[OR_MAX_ORDER];
         if (st->cmask[beta]) { core_key[beta] = INFINITY; continue; }
         unflatten(st, beta, j);
         double g = st->core[beta];
@@ -360,8 +371,10 @@ void or_responsibility(const or_state *st, double *core_key, double **factor_key
     }
     for (int n = 0; n < st->order; ++n) {
         int32_t J = st->ranks[n];
-        ksum *k = (ksum *)malloc((size_t)J * sizeof(ksum));
+#pragma omp parallel for schedule(dynamic, 16)
         for (int64_t i = 0; i < st->dims[n]; ++i) {
+            double delta[OR_MAX_RANK];
+            ksum k[OR_MAX_RANK];
             const double *a = st->factors[n] + i * J;
             for (int32_t t = 0; t < J; ++t) k[t].s = k[t].c = 0.0;
             for (int64_t p = st->row_ptr[n][i]; p < st->row_ptr[n][i + 1]; ++p) {
@@ -375,7 +388,6 @@ void or_responsibility(const or_state *st, double *core_key, double **factor_key
             for (int32_t t = 0; t < J; ++t)
                 factor_key[n][i * J + t] = st->fmask[n][i * J + t] ? INFINITY : ks_val(&k[t]);
         }
-        free(k);
     }
     free(res);
 }
