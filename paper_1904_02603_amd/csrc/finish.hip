@@ -114,8 +114,10 @@ hipError_t launch_count_nonzeros(vest_ctx *c, int64_t *counts)
 {
     uint64_t *dev = reinterpret_cast<uint64_t *>(c->red);
     for (int n = 0; n <= c->N; ++n) {
-        const double *v = n < c->N ? c->A[n] : c->core;
-        const int64_t len = n < c->N ? c->d.dims[n] * c->J : c->G;
+        // the caller's arrays and flat order (the copies of a padded context
+        // hold them as well, see pad.hip)
+        const double *v = n < c->N ? c->uA[n] : c->ucore;
+        const int64_t len = n < c->N ? c->d.dims[n] * c->uranks[n] : c->uG;
         hipError_t e = nz_scan(c, v, len, dev + n);
         if (e != hipSuccess) return e;
     }
@@ -130,8 +132,8 @@ hipError_t launch_export(vest_ctx *c, int64_t *const *fi, double *const *fv, int
 {
     uint64_t *dev = reinterpret_cast<uint64_t *>(c->red);
     for (int n = 0; n <= c->N; ++n) {
-        const double *v = n < c->N ? c->A[n] : c->core;
-        const int64_t len = n < c->N ? c->d.dims[n] * c->J : c->G;
+        const double *v = n < c->N ? c->uA[n] : c->ucore;
+        const int64_t len = n < c->N ? c->d.dims[n] * c->uranks[n] : c->uG;
         hipError_t e = nz_scan(c, v, len, dev);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_nzwrite, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, c->stream, v, len, c->pv_in,
@@ -150,22 +152,28 @@ struct FacIn {
 };
 
 // One level of the looped contraction over the other modes' indices
-// o_L (order-8 shapes, where the unrolled dense form is not compiled): the
-// running product w of the factor values chosen so far, o the flat index of
-// the indices chosen so far.
+// o_L (order-8 shapes, where the unrolled dense form is not compiled),
+// factored: level L returns the partial sum over its subtree,
+// d_L[j] = sum_b r[L][b] d_{L+1}(b)[j], so that no floating-point sum has
+// more than J terms; o is the flat index of the indices chosen so far.
 template <int L, int N, int J, typename T>
-__device__ __forceinline__ void heldout_level(const T *__restrict__ Gp, const T (&r)[N - 1][J], T w, int o, T (&d)[J])
+__device__ __forceinline__ void heldout_level(const T *__restrict__ Gp, const T (&r)[N - 1][J], int o, T (&d)[J])
 {
     constexpr int S = ipow(J, N - 1);
+#pragma unroll
+    for (int j = 0; j < J; ++j) d[j] = T(0);
 #pragma nounroll
     for (int b = 0; b < J; ++b) {
-        const T v = w * pick<J, T>(r[L], b);
+        const T x = pick<J, T>(r[L], b);
         const int oo = o * J + b;
         if constexpr (L == N - 2) {
 #pragma unroll
-            for (int j = 0; j < J; ++j) d[j] = vfma(v, Gp[j * S + oo], d[j]);
+            for (int j = 0; j < J; ++j) d[j] = vfma(x, Gp[j * S + oo], d[j]);
         } else {
-            heldout_level<L + 1, N, J, T>(Gp, r, v, oo, d);
+            T sub[J];
+            heldout_level<L + 1, N, J, T>(Gp, r, oo, sub);
+#pragma unroll
+            for (int j = 0; j < J; ++j) d[j] = vfma(x, sub[j], d[j]);
         }
     }
 }
@@ -204,9 +212,7 @@ __global__ void __launch_bounds__(256) k_heldout(const int32_t *__restrict__ idx
         } else {
             // looped form: delta_j = sum_o Gp[j][o] prod_k r[k][o_k], o in flat
             // order over the other modes (mode 0's permuted core is row-major)
-#pragma unroll
-            for (int j = 0; j < J; ++j) d[j] = T(0);
-            heldout_level<0, N, J, T>(Gp, r, T(1), 0, d);
+            heldout_level<0, N, J, T>(Gp, r, 0, d);
         }
         T b = own[0] * d[0];
 #pragma unroll

@@ -89,6 +89,12 @@ __device__ __forceinline__ void row_epilogue(const RowArgs<N, J, T> &a, int row,
 // combinations of nonzero values of its entry's other-mode rows whose core
 // column is nonzero, so the work per entry is proportional to the number of
 // surviving terms instead of J^N.
+// Up to order 4 the walk carries the running product w of the chosen factor
+// values down to the last level and adds w * r * G into d (at most J^3 terms
+// per sum).  From order 5 it is factored: level L returns the partial sum over
+// its subtree, d_L[j] = sum_b r[L][b] d_{L+1}(b)[j], so that no floating-point
+// sum has more than J terms (one running sum over the J^(N-1) columns of a
+// high-order core loses accuracy with its length).
 template <int L, int N, int J, typename T>
 __device__ __forceinline__ void gather_level(const T *__restrict__ Gt, const uint32_t *__restrict__ Gnz,
                                              const T (&r)[N - 1][J], const uint32_t (&m)[N - 1], T w, int o,
@@ -108,6 +114,34 @@ __device__ __forceinline__ void gather_level(const T *__restrict__ Gt, const uin
             }
         } else {
             gather_level<L + 1, N, J, T>(Gt, Gnz, r, m, v, oo, d);
+        }
+    }
+}
+
+template <int L, int N, int J, typename T>
+__device__ __forceinline__ void gather_level_factored(const T *__restrict__ Gt, const uint32_t *__restrict__ Gnz,
+                                                      const T (&r)[N - 1][J], const uint32_t (&m)[N - 1], int o,
+                                                      T (&d)[J])
+{
+#pragma unroll
+    for (int j = 0; j < J; ++j) d[j] = T(0);
+    uint32_t bits = m[L];
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1;
+        const T x = pick<J, T>(r[L], b);
+        const int oo = o * J + b;
+        if constexpr (L == N - 2) {
+            if ((Gnz[oo >> 5] >> (oo & 31)) & 1u) {
+                const T *g = Gt + oo * J;
+#pragma unroll
+                for (int j = 0; j < J; ++j) d[j] = vfma(x, g[j], d[j]);
+            }
+        } else {
+            T sub[J];
+            gather_level_factored<L + 1, N, J, T>(Gt, Gnz, r, m, oo, sub);
+#pragma unroll
+            for (int j = 0; j < J; ++j) d[j] = vfma(x, sub[j], d[j]);
         }
     }
 }
@@ -140,7 +174,10 @@ __device__ __forceinline__ void delta_gather(const T *__restrict__ Gt, const uin
         for (int t = 0; t < J; ++t) b |= (r[k][t] != T(0) ? 1u : 0u) << t;
         m[k] &= b;
     }
-    gather_level<0, N, J, T>(Gt, Gnz, r, m, T(1), 0, d);
+    if constexpr (N <= 4)
+        gather_level<0, N, J, T>(Gt, Gnz, r, m, T(1), 0, d);
+    else
+        gather_level_factored<0, N, J, T>(Gt, Gnz, r, m, 0, d);
 }
 
 template <int N, int J, typename T>

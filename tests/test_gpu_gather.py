@@ -2,7 +2,7 @@
 
 The gather form (vest_set_kernel(VEST_KERNEL_GATHER)) evaluates Eq. 11 over
 the nonzero factor values and nonzero core columns only; it must reproduce the
-oracle's full sums to the FP64 bar (1e-10 normwise relative, keys 1e-9, masks
+oracle's full sums to the FP64 bar (1e-10 element-wise relative above a floor, keys too, masks
 identical) at any sparsity, including none.  Random marking tables of 0, 60
 and 95 % are planted on core and factors (marked elements are zero, Sec. 3.3).
 """
@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from oracle.oracle import REG_L1, REG_LF
-from test_gpu_parity import IDS, SHAPES, V, assert_state, keys_close, make, pair, say
+from test_gpu_parity import IDS, SHAPES, V, assert_state, keys_close, make, pair, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -148,5 +148,4 @@ def test_schedule_loop_with_and_without_compaction_agree():
     for a, b in zip(*hist):
         assert abs(a - b) <= 1e-10 * abs(a)
     for n in range(3):
-        a, b = ctxs[0].factors[n].cpu().numpy(), ctxs[1].factors[n].cpu().numpy()
-        assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
+        assert rel_err(ctxs[1].factors[n], ctxs[0].factors[n]) <= 1e-10

@@ -1,21 +1,26 @@
 """GPU checks of the FP32 and BF16 forms against the FP64 oracle.
 
-In both forms the delta contraction and the row sums run in FP32 (the first
-contraction stage of order-3 factor sweeps on matrix cores: FP32 operands in
-the FP32 form, core and last other-mode factor row rounded to BF16 in the BF16
-form); the division, soft threshold, keys and the masters stay FP64.
+In both forms the delta contraction and the row sums run in FP32; in order-3
+factor sweeps the first contraction stage runs on matrix cores: FP32 operands
+in the FP32 form, and in the BF16 form split-BF16 operands -- the core and
+the last other-mode factor row are each split into x_hi = bf16(x) and
+x_lo = bf16(x - x_hi), and hi*hi + hi*lo + lo*hi is accumulated in FP32, about
+16 significant operand bits (u ~ 2^-17).  Outside order-3 factor sweeps the
+BF16 form computes exactly as the FP32 form.  The division, soft threshold,
+keys and the masters stay FP64.
 
 Bars:
   * after every factor sweep, the loss of the GPU state (Eq. 1, evaluated in
     FP64) is within LOSS_BAR[form] relative of the oracle's.  The sweep is a
-    set of exact one-dimensional minimisations; an operand error of relative
-    size u moves each minimiser by O(u) and, the loss being stationary there,
-    the loss by O(u^2) relative (u = 2^-24 for FP32, 2^-9 for BF16, bars with
-    a safety factor for the condition of the row statistics V);
-  * FP32 factors element-wise within 1e-4 (normwise by the max) of the
-    oracle's after each sweep.  BF16 factors are not compared element-wise:
-    along near-flat directions of an ill-conditioned V, O(u) operand errors
-    move a minimiser far without changing the loss;
+    set of exact one-dimensional minimisations, so the loss is stationary at
+    each minimiser and moves by the square of the operand error times the
+    condition of the row statistics V (bars with a safety factor);
+  * the factor matrices within 1e-4 relative RMSE (||gpu - oracle|| /
+    ||oracle||) of the oracle's after each sweep, FP32 and BF16; the
+    element-wise error (above a floor of 1e-2 of the largest magnitude) is
+    printed beside it.  Element-wise bars are not applied to these forms:
+    along near-flat directions of an ill-conditioned V an O(u) operand error
+    moves a minimiser far without changing the loss;
   * after five full iterations of the 100^3 planted workload the relative RE
     gap is at most 1e-4 in both forms.
 """
@@ -24,7 +29,7 @@ import pytest
 import torch
 
 from paper_1904_02603_amd import synth
-from test_gpu_parity import REG_L1, REG_LF, V, make, pair, rel_err, say
+from test_gpu_parity import REG_L1, REG_LF, V, make, pair, rel_err, rms_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -58,11 +63,11 @@ def test_lowp_factor_sweeps_track_oracle(case, prec, reg):
         o.sweep_factor(n)
         gl, ol = g.loss(), o.loss()
         gap = abs(gl["loss"] - ol["loss"]) / ol["loss"]
-        fe = rel_err(g.factors[n], o.factors[n])
-        say("  mode %d: loss gap %.3e, factor err %.3e" % (n, gap, fe))
+        fe = rel_err(g.factors[n], o.factors[n], floor=1e-2)
+        fr = rms_err(g.factors[n], o.factors[n])
+        say("  mode %d: loss gap %.3e, factor rel RMSE %.3e, element-wise (floor 1e-2) %.3e" % (n, gap, fr, fe))
         assert gap <= LOSS_BAR[prec], (n, gap)
-        if prec == "FP32":
-            assert fe <= 1e-4, (n, fe)
+        assert fr <= 1e-4, (n, fr)
 
 
 @pytest.mark.parametrize("prec", ["FP32", "BF16"])
@@ -74,7 +79,8 @@ def test_lowp_form_re_within_1e4_after_five_iterations(prec):
         o.iteration()
     gl, ol = g.loss(), o.loss()
     gap = abs(gl["re"] - ol["re"]) / ol["re"]
-    say("%s relative RE gap %.3e, factor rel err %.3e" % (prec, gap, rel_err(g.factors[0], o.factors[0])))
+    say("%s relative RE gap %.3e, factor rel RMSE %s" % (
+        prec, gap, ["%.2e" % rms_err(g.factors[n], o.factors[n]) for n in range(3)]))
     assert gap <= 1e-4
 
 

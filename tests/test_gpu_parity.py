@@ -2,11 +2,17 @@
 
 Each test feeds the same seeded state to libvest (through the ctypes binding)
 and to the oracle, runs the same step on both and compares element by element.
-Bar (FP64 path): factors, core, loss and keys within 1e-10 normwise relative
-error (max |gpu - oracle| / max |oracle| per tensor); prune masks identical.
-The GPU sums in a different order than the oracle's compensated sums, so
-bit equality of values is not expected; masks are integer decisions and must
-match exactly.
+
+Bar (FP64 path), per tensor (each factor matrix, the core, every key array):
+    |gpu - oracle| <= RTOL * max(|oracle|, FLOOR * max|oracle|)
+element by element, RTOL = 1e-10 and FLOOR = 1e-4: every element whose
+magnitude is at least 1e-4 of the tensor's largest is within 1e-10 of its
+own value; smaller ones (near-cancelled updates, whose rounding error scales
+with the magnitude of the summed terms rather than with the result) are held
+to 1e-14 of the tensor's largest.  Loss terms within 1e-10 relative (1e-12
+where stated).  Prune masks identical.  The GPU sums in a different order
+than the oracle's compensated sums, so bit equality of values is not
+expected; masks are integer decisions and must match exactly.
 """
 import numpy as np
 import pytest
@@ -18,6 +24,7 @@ from paper_1904_02603_amd import synth
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-10
+FLOOR = 1e-4
 
 
 def V():
@@ -46,11 +53,26 @@ def pair(p, reg, lam, precision=0, fmask=None, cmask=None):
     return g, o
 
 
-def rel_err(gpu, ref):
-    a = gpu.detach().cpu().numpy() if torch.is_tensor(gpu) else np.asarray(gpu)
-    b = np.asarray(ref)
+def _np(x):
+    return x.detach().cpu().numpy() if torch.is_tensor(x) else np.asarray(x)
+
+
+def rel_err(gpu, ref, floor=FLOOR):
+    """max over elements of |gpu - ref| / max(|ref|, floor * max|ref|)
+    (finite reference elements only)."""
+    a, b = _np(gpu), _np(ref)
+    fin = np.isfinite(b)
+    a, b = a[fin], b[fin]
+    if b.size == 0:
+        return 0.0
     scale = max(float(np.abs(b).max()), 1e-300)
-    return float(np.abs(a - b).max()) / scale
+    return float((np.abs(a - b) / np.maximum(np.abs(b), floor * scale)).max())
+
+
+def rms_err(gpu, ref):
+    """Relative RMSE: ||gpu - ref||_2 / ||ref||_2."""
+    a, b = _np(gpu), _np(ref)
+    return float(np.sqrt(((a - b) ** 2).sum()) / max(np.sqrt((b * b).sum()), 1e-300))
 
 
 def assert_state(g, o, rtol=RTOL, what=""):
@@ -123,11 +145,8 @@ def keys_close(gk, ok, what):
     a = gk.detach().cpu().numpy()
     b = np.asarray(ok)
     assert np.array_equal(np.isinf(a), np.isinf(b)), what + ": +inf pattern"
-    fin = np.isfinite(b)
-    if fin.any():
-        scale = float(np.abs(b[fin]).max())
-        err = float(np.abs(a[fin] - b[fin]).max()) / max(scale, 1e-300)
-        assert err <= 1e-9, "%s: rel err %.3e" % (what, err)
+    err = rel_err(a, b)
+    assert err <= RTOL, "%s: element-wise rel err %.3e" % (what, err)
 
 
 @pytest.mark.parametrize("reg", [REG_LF, REG_L1], ids=["LF", "L1"])
