@@ -432,6 +432,209 @@ def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
             "iterations_per_job": 10}
 
 
+def gen_workload(name):
+    """Seeded inputs of a named workload (run in a worker process)."""
+    from paper_1904_02603_amd import synth
+    synth.THREADS = 4      # leave host cores to the process that drives the GPU
+    t0 = time.perf_counter()
+    p = synth.workload(name)
+    p.pop("planted", None)
+    p["gen_s"] = time.perf_counter() - t0
+    return p
+
+
+def sampled_rows_vs_oracle(p, mode, got, rows):
+    """The oracle's Alg. 4 update of sampled rows of `mode` from the initial
+    state (rows are independent given the other modes), against the rows a
+    GPU form produced in its first sweep of that mode.  Returns the oracle's
+    rows and its time."""
+    from oracle.oracle import Oracle
+    o = Oracle(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"])
+    t0 = time.perf_counter()
+    for i in rows:
+        o.update_row(mode, int(i))
+    dt = time.perf_counter() - t0
+    ref = o.factors[mode][rows].copy()
+    del o
+    return ref, dt
+
+
+def pick_rows(idx, mode, dim, k, max_len, seed):
+    import numpy as np
+    cnt = np.bincount(idx[:, mode], minlength=dim)
+    ok = np.flatnonzero((cnt > 0) & (cnt <= max_len))
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(ok, min(k, ok.size), replace=False))
+    return rows, int(cnt[rows].sum())
+
+
+def rel_errs(got, ref):
+    import numpy as np
+    d = np.abs(got - ref)
+    s = np.abs(ref).max()
+    return {"elementwise_floor_1e-4": float((d / np.maximum(np.abs(ref), 1e-4 * s)).max()),
+            "rel_rmse": float(np.sqrt((d * d).sum() / max((ref * ref).sum(), 1e-300)))}
+
+
+def rating_leg(p, steps, warmup):
+    """Rating-shaped Zipf tensor, 10^8 entries: FP64, FP32 and split-BF16
+    forms from the same start, `warmup` + `steps` iterations each (factor
+    sweeps + core sweep + loss); the first mode-0 sweep's sampled rows against
+    the oracle; FP32 / BF16 state against FP64 after the run."""
+    import numpy as np
+    import torch
+    from paper_1904_02603_amd import vest
+    N, nnz = p["idx"].shape[1], p["idx"].shape[0]
+    dims = [f.shape[0] for f in p["factors"]]
+    J = p["factors"][0].shape[1]
+    rows, row_entries = pick_rows(p["idx"], 0, dims[0], 48, 4000, 7)
+    out = {"workload": "rating-zipf-500k.20k.2k-nnz1e8-r10", "dims": dims, "nnz": nnz, "ranks": [J] * N,
+           "reg": "L_1", "lambda": p["lam"], "iterations_timed": steps, "warmup": warmup,
+           "input_generation_s": p.get("gen_s")}
+    first_rows, final = {}, {}
+    for name, prec in [("fp64", vest.FP64), ("fp32", vest.FP32), ("bf16", vest.BF16)]:
+        ctx = vest.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"],
+                               precision=prec)
+        lg = EventLog(torch.cuda.current_stream())
+        ctx.sweep_factor(0)
+        first_rows[name] = ctx.factors[0][torch.as_tensor(rows, device="cuda")].cpu().numpy()
+        for n in range(1, N):
+            ctx.sweep_factor(n)
+        ctx.sweep_core()
+        for _ in range(max(0, warmup - 1)):
+            ctx.iteration()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for n in range(N):
+                lg.timed("sweep_factor", lambda: ctx.sweep_factor(n))
+            lg.timed("sweep_core", ctx.sweep_core)
+            L = lg.timed("loss", ctx.loss)
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t0) * 1e3 / steps
+        ms = lg.ms()
+        ts = 8 if prec == vest.FP64 else 4
+        alg = sweep_alg_bytes(N, nnz, dims, J, ts)
+        r = {"ms_per_step": ms_step, "value": N * nnz / (ms_step / 1e3),
+             "sweep_only_value": nnz / (ms["sweep_factor"] / 1e3), "breakdown_ms": ms, "final_re": L["re"],
+             "sweep_roofline": {"bound": "hbm", "achieved": alg / (ms["sweep_factor"] / 1e3) / 1e9,
+                                "peak": HBM_PEAK, "unit": "GB/s",
+                                "frac": alg / (ms["sweep_factor"] / 1e3) / 1e9 / HBM_PEAK,
+                                "algorithmic_bytes_per_launch": alg}}
+        if name == "bf16":
+            mf = 2 * J ** N * nnz   # first contraction stage on matrix cores, algorithmic
+            r["sweep_mfma"] = {"achieved": mf / (ms["sweep_factor"] / 1e3) / 1e12, "peak": 2500.0,
+                               "unit": "TFLOP/s", "algorithmic_flops_per_launch": mf,
+                               "note": "split form issues three products per algorithmic one"}
+        final[name] = ([f.clone() for f in ctx.factors] + [ctx.core.clone()], L["re"])
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+        out[name] = r
+        log("  %s: %.2f ms/step, factor sweep %.3f ms, core sweep %.3f ms" % (
+            name, ms_step, ms["sweep_factor"], ms["sweep_core"]))
+    ref_t, ref_re = final["fp64"]
+    for name in ("fp32", "bf16"):
+        t, re_ = final[name]
+        out[name]["vs_fp64"] = {"re_gap": abs(re_ - ref_re) / ref_re,
+                                "rel_rmse_factors": max(float(torch.sqrt(((a - b) ** 2).sum() / (b * b).sum()))
+                                                        for a, b in zip(t[:-1], ref_t[:-1])),
+                                "rel_rmse_core": float(torch.sqrt(((t[-1] - ref_t[-1]) ** 2).sum()
+                                                                  / (ref_t[-1] ** 2).sum()))}
+    del final, ref_t
+    ref, dt = sampled_rows_vs_oracle(p, 0, None, rows)
+    out["oracle_sample"] = {"rows": int(rows.size), "entries": row_entries, "oracle_s": dt,
+                            "oracle_entry_updates_per_s": row_entries / dt,
+                            "what": "first mode-0 sweep from the initial state, sampled rows of <= 4000 entries",
+                            **{name: rel_errs(first_rows[name], ref) for name in first_rows}}
+    return out
+
+
+def order4_auto_leg(p, iters, target):
+    """Order-4 Zipf tensor, 5e7 entries, ranks 8^4: VeST^auto (elbow rule,
+    sparsity cap `target`) through the host schedule in FP32 and FP64 from the
+    same start, time and RE of every iteration; dense-phase and final
+    (pruned, compacted) factor-sweep rooflines of the FP32 form; sampled rows
+    of the first mode-0 sweep against the oracle."""
+    import numpy as np
+    import torch
+    from paper_1904_02603_amd import vest
+    from paper_1904_02603_amd.schedule import PruneSchedule, run
+    N, nnz = p["idx"].shape[1], p["idx"].shape[0]
+    dims = [f.shape[0] for f in p["factors"]]
+    J = p["factors"][0].shape[1]
+    rows, row_entries = pick_rows(p["idx"], 0, dims[0], 48, 4000, 8)
+    out = {"workload": "planted-zipf-50k.50k.1k.24-nnz5e7-r8", "dims": dims, "nnz": nnz, "ranks": [J] * N,
+           "reg": "L_F", "lambda": p["lam"], "schedule": "VeST^auto, elbow 0.05, cap %.2f" % target,
+           "max_iterations": iters, "input_generation_s": p.get("gen_s")}
+    first_rows, finals = {}, {}
+    for name, prec in [("fp32", vest.FP32), ("fp64", vest.FP64)]:
+        ctx = vest.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"],
+                               precision=prec)
+        lg = EventLog(torch.cuda.current_stream())
+        # dense phase: the first iteration's factor sweeps, timed
+        for n in range(N):
+            lg.timed("dense_sweep", lambda: ctx.sweep_factor(n))
+            if n == 0:
+                first_rows[name] = ctx.factors[0][torch.as_tensor(rows, device="cuda")].cpu().numpy()
+        torch.cuda.synchronize()
+        ctx.close()
+        ctx = vest.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"],
+                               precision=prec)
+        hist = []
+        tl = [time.perf_counter()]
+
+        def rec(d):
+            tl.append(time.perf_counter())
+            d = dict(d)
+            d["ms"] = (tl[-1] - tl[-2]) * 1e3
+            hist.append(d)
+        run(ctx, iters, PruneSchedule(mode="auto", target=target), log=rec, compact_every=5, normalize=False)
+        live = ctx.layout_stats(0)["nnz"]
+        for _ in range(3):
+            for n in range(N):
+                lg.timed("final_sweep", lambda: ctx.sweep_factor(n))
+        torch.cuda.synchronize()
+        ms = lg.ms()
+        fl = sweep_flops_per_entry(N, J) * nnz
+        peak = PEAK["f32"] if prec == vest.FP32 else PEAK["f64"]
+        ts = 4 if prec == vest.FP32 else 8
+        alg_final = live * ((N - 1) * 4 + ts) + sum(d * J * 8 for d in dims) * (N + 1) / N
+        r = {"iterations": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in h.items()} for h in hist],
+             "final_re": hist[-1]["re"], "final_sparsity": hist[-1]["sparsity"],
+             "prune_steps": sum(1 for h in hist if h["pruned"]),
+             "dense_sweep_ms": ms["dense_sweep"],
+             "dense_sweep_roofline": {"bound": "alu", "achieved": fl / (ms["dense_sweep"] / 1e3) / 1e12,
+                                      "peak": peak, "unit": "TFLOP/s",
+                                      "frac": fl / (ms["dense_sweep"] / 1e3) / 1e12 / peak,
+                                      "flops_per_launch": fl},
+             "dense_entry_updates_per_s": nnz / (ms["dense_sweep"] / 1e3),
+             "final_sweep_ms": ms["final_sweep"], "live_entries_final": live,
+             "final_entry_updates_per_s": nnz / (ms["final_sweep"] / 1e3),
+             "final_sweep_roofline": {"bound": "hbm", "achieved": alg_final / (ms["final_sweep"] / 1e3) / 1e9,
+                                      "peak": HBM_PEAK, "unit": "GB/s",
+                                      "frac": alg_final / (ms["final_sweep"] / 1e3) / 1e9 / HBM_PEAK,
+                                      "algorithmic_bytes_per_launch": alg_final}}
+        finals[name] = ([m.clone() for m in ctx.factor_masks_bool()] + [ctx.cmask.bool().clone()], hist[-1]["re"])
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+        out[name] = r
+        log("  %s: %d iterations, %d prune steps, sparsity %.3f, RE %.6f; dense sweep %.2f ms, final sweep %.3f ms"
+            % (name, len(hist), r["prune_steps"], r["final_sparsity"], r["final_re"], ms["dense_sweep"],
+               ms["final_sweep"]))
+    m32, re32 = finals["fp32"]
+    m64, re64 = finals["fp64"]
+    out["fp32"]["vs_fp64"] = {"re_gap": abs(re32 - re64) / re64,
+                              "mask_elements_differing": int(sum(int((a ^ b).sum()) for a, b in zip(m32, m64)))}
+    ref, dt = sampled_rows_vs_oracle(p, 0, None, rows)
+    out["oracle_sample"] = {"rows": int(rows.size), "entries": row_entries, "oracle_s": dt,
+                            "oracle_entry_updates_per_s": row_entries / dt,
+                            "what": "first mode-0 sweep from the initial state, sampled rows of <= 4000 entries",
+                            **{name: rel_errs(first_rows[name], ref) for name in first_rows}}
+    return out
+
+
 TRAFFIC = {   # committed counter summary and the sources of the kernel it measured
     "slab": ("traffic_k_slab_planted-1e5^3-nnz1e7-r10_fp64.md", ["core.hip", "device.h", "internal.h"]),
     "sweep": ("traffic_k_rowgroup_sweep_planted-1e5^3-nnz1e7-r10_fp64.md", ["rowgroup.hip", "device.h", "internal.h"]),
@@ -559,6 +762,10 @@ def main():
     ap.add_argument("--serve-arena-gb", type=float, default=32.0)
     ap.add_argument("--serve-calib", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--config3", type=int, default=1, help="run the 1e8-entry rating-tensor leg (BF16, L_1)")
+    ap.add_argument("--config4", type=int, default=1, help="run the order-4 5e7-entry VeST^auto leg (FP32)")
+    ap.add_argument("--big-steps", type=int, default=10, help="timed iterations of the 1e8-entry leg")
+    ap.add_argument("--auto-iters", type=int, default=20, help="iteration cap of the VeST^auto leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--scaling", action="store_true",
@@ -586,6 +793,16 @@ def main():
                           "timing": "wall clock per Alg. 2 iteration (factor sweeps + core sweep + loss), 3 after 1",
                           "results": scaling_study()}))
         return
+    pool, futs = None, {}
+    if args.config3 or args.config4:
+        # inputs of the large legs drawn in worker processes while the headline runs
+        from concurrent.futures import ProcessPoolExecutor
+        import multiprocessing as mp
+        pool = ProcessPoolExecutor(max_workers=2, mp_context=mp.get_context("spawn"))
+        if args.config3:
+            futs["config3"] = pool.submit(gen_workload, "rating-zipf-500k.20k.2k-nnz1e8-r10")
+        if args.config4:
+            futs["config4"] = pool.submit(gen_workload, "planted-zipf-50k.50k.1k.24-nnz5e7-r8")
     t0 = time.perf_counter()
     log("generating workload %s ..." % args.workload)
     p = synth.workload(args.workload, nnz=args.nnz)
@@ -645,9 +862,28 @@ def main():
         log("  %.2f jobs/s, p50 %.3f s, p99 %.3f s (serial %.2f jobs/s)" % (
             serving["jobs_per_s"], serving["latency_p50_s"], serving["latency_p99_s"], serving["serial_jobs_per_s"]))
     cpu = None
+    for f in futs.values():   # the CPU baseline runs with no input generation beside it
+        f.exception()
     if args.cpu_seconds > 0:
         log("oracle CPU baseline ...")
         cpu = cpu_baseline(p, args.cpu_seconds)
+    dims0, reg0, lam0 = [int(f.shape[0]) for f in p["factors"]], p["reg"], p["lam"]
+    del p
+    legs_big = {}
+    if "config3" in futs:
+        log("rating-shaped Zipf tensor, 1e8 entries (waiting for its inputs) ...")
+        p3 = futs["config3"].result()
+        log("  inputs drawn in %.1f s" % p3["gen_s"])
+        legs_big["rating_zipf_1e8"] = rating_leg(p3, args.big_steps, 1)
+        del p3
+    if "config4" in futs:
+        log("order-4 Zipf tensor, 5e7 entries, VeST^auto (waiting for its inputs) ...")
+        p4 = futs["config4"].result()
+        log("  inputs drawn in %.1f s" % p4["gen_s"])
+        legs_big["order4_zipf_auto"] = order4_auto_leg(p4, args.auto_iters, 0.95)
+        del p4
+    if pool is not None:
+        pool.shutdown()
 
     named = args.workload == DEFAULT_WORKLOAD and args.nnz is None
     slab_gbs = f64["slab_alg_bytes_per_launch"] / (f64["slab_kernel_ms"] / 1e3) / 1e9
@@ -667,8 +903,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "dims": [int(f.shape[0]) for f in p["factors"]], "nnz": nnz,
-                   "ranks": [J] * N, "reg": "L_F" if p["reg"] == 0 else "L_1", "lambda": p["lam"],
+        "config": {"workload": args.workload, "dims": dims0, "nnz": nnz,
+                   "ranks": [J] * N, "reg": "L_F" if reg0 == 0 else "L_1", "lambda": lam0,
                    "core": "dense", "sweeps_timed": args.steps,
                    "step": "factor sweeps (all modes) + core sweep + loss; no pruning",
                    "forms": "FP64 (value) vs FP32 / split-BF16 (keys fp32, bf16)"},
@@ -710,6 +946,7 @@ def main():
         out["pruned_phase"] = sparse
     if serving is not None:
         out["serving"] = serving
+    out.update(legs_big)
     if args.nnz is not None:
         out["config"]["note"] = "reduced nnz: not the named workload"
     print(json.dumps(out))

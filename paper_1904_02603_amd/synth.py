@@ -21,6 +21,7 @@ import math
 import numpy as np
 
 SEED_BASE = 20190402
+THREADS = None      # worker threads of planted_values (None: up to 16)
 
 
 def _zipf_sampler(I, s, rng):
@@ -89,15 +90,20 @@ def observed_indices(dims, nnz, rng, zipf=None):
     return np.ascontiguousarray(got, dtype=np.int32)
 
 
-def planted_values(idx, core, factors, chunk=1 << 17):
+def planted_values(idx, core, factors, chunk=1 << 17, threads=None):
     """Planted model value at every observed entry (Tucker model, Sec. 2.2).
 
     Evaluated by contracting the core with one factor row per mode, last mode
-    first, with numpy tensordot on chunks of entries.
+    first, with numpy tensordot on chunks of entries.  Chunks are independent
+    and computed the same way whichever thread takes them, so the values do
+    not depend on the thread count.
     """
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     N = idx.shape[1]
     out = np.empty(idx.shape[0], dtype=np.float64)
-    for s in range(0, idx.shape[0], chunk):
+
+    def one(s):
         sl = idx[s:s + chunk]
         m = sl.shape[0]
         t = np.broadcast_to(core, (m,) + core.shape)
@@ -105,6 +111,15 @@ def planted_values(idx, core, factors, chunk=1 << 17):
             rows = factors[n][sl[:, n]]                     # [m, J_n]
             t = np.einsum("m...j,mj->m...", t, rows)
         out[s:s + chunk] = t
+
+    starts = range(0, idx.shape[0], chunk)
+    nt = threads or THREADS or min(16, os.cpu_count() or 1)
+    if nt > 1 and len(starts) > 1:
+        with ThreadPoolExecutor(nt) as ex:
+            list(ex.map(one, starts))
+    else:
+        for s in starts:
+            one(s)
     return out
 
 
@@ -169,7 +184,7 @@ WORKLOADS = {
 
 
 # Serving workload: ranks with a compiled kernel instance in 4..10 per order.
-SERVING_RANKS = {3: (4, 5, 6, 8, 10), 4: (4, 5, 6, 8)}
+SERVING_RANKS = {3: (4, 5, 6, 7, 8, 9, 10), 4: (4, 5, 6, 7, 8, 9, 10)}
 
 
 def rating_values(idx, dims, rng):
@@ -208,7 +223,9 @@ def serving_jobs(n_jobs, tensors, seed=SEED_BASE + 6):
     draws a tensor, ranks uniform over SERVING_RANKS[N], L_F / L_1 with equal
     probability (lambda 0.01 / 0.1), FP32 / BF16 form with equal
     probability, 10 iterations, and a seed for its U[0, 1) initial state
-    (serving_init)."""
+    (serving_init).  The BF16 form differs from the FP32 form only in the
+    order-3 factor sweep (matrix cores), so an order-4 job that draws BF16 is
+    labelled and run as FP32."""
     rng = np.random.Generator(np.random.PCG64(seed))
     jobs = []
     for i in range(n_jobs):
@@ -217,7 +234,7 @@ def serving_jobs(n_jobs, tensors, seed=SEED_BASE + 6):
         J = int(rng.choice(SERVING_RANKS[N]))
         reg = int(rng.integers(0, 2))
         jobs.append({"tensor": k, "ranks": (J,) * N, "reg": reg, "lam": 0.01 if reg == 0 else 0.1,
-                     "form": "FP32" if rng.random() < 0.5 else "BF16", "iterations": 10,
+                     "form": "FP32" if (rng.random() < 0.5 or N != 3) else "BF16", "iterations": 10,
                      "init_seed": (seed, i)})
     return jobs
 
