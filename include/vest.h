@@ -46,7 +46,8 @@ enum {
     VEST_ENOSPC = -2,   /* workspace too small                                         */
     VEST_EDEVICE = -3,  /* HIP runtime error; the context must be destroyed             */
     VEST_ESTATE = -4,   /* call out of order (e.g. vest_prune before vest_responsibility) */
-    VEST_EUNSUPPORTED = -5 /* valid problem, but no kernel instance for this (order, rank) */
+    VEST_EUNSUPPORTED = -5 /* valid problem, but no kernel instance for (order, max rank): ranks 2..10
+                              at orders 3 and 4, 2..3 at order 2, 3 at orders 5..10 */
 };
 
 enum { VEST_REG_LF = 0, VEST_REG_L1 = 1 };   /* Eq. 1 / Eq. 2 */
@@ -73,7 +74,13 @@ typedef struct {
                                           (Eq. 1 / Eq. 2, Table 1)                     */
     int64_t nnz;                       /* |Omega| >= 1                                 */
     int64_t dims[VEST_MAX_ORDER];      /* I_n >= 1, I_n < 2^31                         */
-    int32_t ranks[VEST_MAX_ORDER];     /* J_n, 1..VEST_MAX_RANK                        */
+    int32_t ranks[VEST_MAX_ORDER];     /* J_n, 1..VEST_MAX_RANK; may differ per mode
+                                          (Table 1): the context then runs the kernels
+                                          of J = max J_n on a padded copy of the model
+                                          in its workspace, every element outside the
+                                          caller's J_1 x .. x J_N model marked, and
+                                          copies the caller's part back after every
+                                          call that changes it                           */
 } vest_desc;
 
 typedef struct vest_ctx vest_ctx;      /* opaque, library-owned host object */

@@ -42,23 +42,36 @@ int check_desc(const vest_desc *d)
         if (d->dims[n] < 1 || d->dims[n] >= (int64_t(1) << 31)) { set_error("dims[%d] out of range", n); return VEST_EINVAL; }
         if (d->ranks[n] < 1 || d->ranks[n] > VEST_MAX_RANK) { set_error("ranks[%d] outside 1..%d", n, VEST_MAX_RANK); return VEST_EINVAL; }
     }
-    for (int n = 1; n < d->order; ++n)
-        if (d->ranks[n] != d->ranks[0]) {
-            set_error("unequal ranks are not supported by the compiled kernels");
-            return VEST_EUNSUPPORTED;
-        }
+    // unequal ranks run padded to the largest (pad.hip): sizes checked at it
+    const int J = max_rank(d);
     int64_t G = 1;
-    for (int n = 0; n < d->order; ++n) G *= d->ranks[n];
+    for (int n = 0; n < d->order; ++n) G *= J;
     for (int n = 0; n < d->order; ++n)
-        if (d->dims[n] * d->ranks[n] >= (int64_t(1) << 31) || G >= (int64_t(1) << 31)) {
+        if (d->dims[n] * J >= (int64_t(1) << 31) || G >= (int64_t(1) << 31)) {
             set_error("tensor of %d-th factor or core too large", n);
             return VEST_EINVAL;
         }
-    if (!shape_supported(d->order, d->ranks[0])) {
-        set_error("no kernel instance for order %d, rank %d", d->order, d->ranks[0]);
+    if (!shape_supported(d->order, J)) {
+        set_error("no kernel instance for order %d, rank %d", d->order, J);
         return VEST_EUNSUPPORTED;
     }
     return VEST_OK;
+}
+
+int max_rank(const vest_desc *d)
+{
+    int J = 0;
+    for (int n = 0; n < d->order; ++n) J = d->ranks[n] > J ? d->ranks[n] : J;
+    return J;
+}
+
+// The descriptor the kernels run on: every rank set to the largest.
+static vest_desc uniform_desc(const vest_desc *d)
+{
+    vest_desc u = *d;
+    const int J = max_rank(d);
+    for (int n = 0; n < d->order; ++n) u.ranks[n] = J;
+    return u;
 }
 
 int plan_workspace(const vest_desc *d, Plan *p)
@@ -158,6 +171,16 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
         c->gt = take((size_t)c->G * ts);
         c->gnz = (uint32_t *)take(((size_t)(c->G / J) + 31) / 32 * 4);
     }
+    if (c->padded) {
+        for (int n = 0; n < N; ++n) {
+            c->A[n] = (double *)take(c->d.dims[n] * J * 8);
+            c->fmask[n] = (uint32_t *)take(c->d.dims[n] * 4);
+            c->pkey_fac[n] = (double *)take(c->d.dims[n] * J * 8);
+        }
+        c->core = (double *)take(c->G * 8);
+        c->cmask = (uint8_t *)take(c->G);
+        c->pkey_core = (double *)take(c->G * 8);
+    }
     c->red = (double *)take((16 * kLossBlocks + 64) * 8);
     c->flags = (int32_t *)take(64);
     c->sel_hist = (uint32_t *)take((size_t)(VEST_MAX_ORDER + 1) * 4096 * 4);
@@ -172,11 +195,18 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
 
 static void fill_ctx_shape(vest_ctx *c, const vest_desc *d)
 {
-    c->d = *d;
+    c->d = uniform_desc(d);
     c->N = d->order;
-    c->J = d->ranks[0];
+    c->J = max_rank(d);
     c->G = 1;
-    for (int n = 0; n < c->N; ++n) c->G *= c->J;
+    c->uG = 1;
+    c->padded = false;
+    for (int n = 0; n < c->N; ++n) {
+        c->G *= c->J;
+        c->uG *= d->ranks[n];
+        c->uranks[n] = d->ranks[n];
+        c->padded = c->padded || d->ranks[n] != c->J;
+    }
     c->f32 = d->precision != VEST_FP64;
     c->tsize = c->f32 ? 4 : 8;
 }
@@ -264,7 +294,8 @@ int vest_workspace_bytes(const vest_desc *desc, size_t *bytes)
     if (rc) return rc;
     if (!bytes) { set_error("null output"); return VEST_EINVAL; }
     Plan p;
-    rc = plan_workspace(desc, &p);
+    const vest_desc ud = uniform_desc(desc);
+    rc = plan_workspace(&ud, &p);
     if (rc) return rc;
     vest_ctx tmp;
     fill_ctx_shape(&tmp, desc);
@@ -289,7 +320,8 @@ int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const dou
         if (!factors[n] || !factor_mask[n]) { set_error("null factor or mask pointer (mode %d)", n); return VEST_EINVAL; }
     if (((uintptr_t)workspace & 255) != 0) { set_error("workspace must be 256-byte aligned"); return VEST_EINVAL; }
     Plan p;
-    rc = plan_workspace(desc, &p);
+    const vest_desc ud = uniform_desc(desc);
+    rc = plan_workspace(&ud, &p);
     if (rc) return rc;
     size_t need = 0;
     {
@@ -311,12 +343,12 @@ int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const dou
     hipError_t he = hipGetDevice(&c->device);
     if (he != hipSuccess) { int r = device_error(nullptr, he, "hipGetDevice"); delete c; return r; }
     for (int n = 0; n < c->N; ++n) {
-        c->A[n] = factors[n];
-        c->fmask[n] = factor_mask[n];
+        c->A[n] = c->uA[n] = factors[n];
+        c->fmask[n] = c->ufmask[n] = factor_mask[n];
     }
-    c->core = core;
-    c->cmask = core_mask;
-    Bump b{(char *)workspace, 0, ws_bytes};
+    c->core = c->ucore = core;
+    c->cmask = c->ucmask = core_mask;
+    Bump b{(char *)workspace, 0, ws_bytes};   // a padded context re-points A, core and masks into it
     char *scratch = nullptr;
     if (!carve(c, p, b, &scratch)) { delete c; set_error("workspace carve failed"); return VEST_ENOSPC; }
 
@@ -344,7 +376,12 @@ int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const dou
     int64_t *cnt = reinterpret_cast<int64_t *>(c->red + 16 * kLossBlocks + 8);
     int64_t hc[VEST_MAX_ORDER + 1] = {};
     he = hipMemsetAsync(cnt, 0, (c->N + 1) * 8, c->stream);
+    if (he == hipSuccess && c->padded) he = launch_pad_in(c);
     if (he == hipSuccess) he = launch_mask_init(c, cnt);
+    if (he == hipSuccess && c->padded) {   // marked elements of the caller's arrays are zero too
+        for (int n = 0; n < c->N && he == hipSuccess; ++n) he = launch_pad_out_factor(c, n);
+        if (he == hipSuccess) he = launch_pad_out_core(c);
+    }
     if (he == hipSuccess) he = hipMemcpyAsync(hc, cnt, (c->N + 1) * 8, hipMemcpyDeviceToHost, c->stream);
     if (he == hipSuccess) he = hipMemsetAsync(c->rowbuf, 0, c->d.dims[c->N - 1] * c->ldrb * 8, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
@@ -366,6 +403,7 @@ int vest_sweep_factor(vest_ctx *c, int32_t mode)
     if ((rc = ensure_ag(c))) return rc;
     if ((rc = ensure_gp(c, mode))) return rc;
     CALL_HIP(c, launch_rowgroup(c, mode, OP_SWEEP), "factor sweep");
+    if (c->padded) CALL_HIP(c, launch_pad_out_factor(c, mode), "padded copy-out");
     c->e_valid = false;
     c->ms_valid = false;
     c->hdiag_valid = false;
@@ -387,6 +425,7 @@ int vest_sweep_core(vest_ctx *c)
         c->ms_valid = true;
     }
     CALL_HIP(c, launch_core_sweep(c, fused), "core sweep");
+    if (c->padded) CALL_HIP(c, launch_pad_out_core(c), "padded copy-out");
     c->core_version++;
     c->e_valid = true;
     c->hdiag_valid = true;
@@ -407,6 +446,12 @@ int vest_responsibility(vest_ctx *c, double *core_key, double *const *factor_key
     // bound by the vector ALU; they share no buffer they write (the core keys
     // take their own long-row partials), so for large contexts they run on a
     // second stream, forked from and joined back into the context's stream.
+    double *const *ukey_fac = factor_key;
+    double *ukey_core = core_key;
+    if (c->padded) {   // keys of the padded model, copied out at the end
+        core_key = c->pkey_core;
+        factor_key = c->pkey_fac;
+    }
     const bool two = c->d.nnz >= kSideStreamMinNnz;
     if (two && !c->side) {
         CALL_HIP(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "side stream");
@@ -428,6 +473,7 @@ int vest_responsibility(vest_ctx *c, double *core_key, double *const *factor_key
         CALL_HIP(c, hipStreamWaitEvent(c->stream, c->join, 0), "join wait");
     else
         CALL_HIP(c, launch_core_keys(c, core_key, c->stream, c->partials), "core keys");
+    if (c->padded) CALL_HIP(c, launch_pad_out_keys(c, ukey_core, ukey_fac), "padded key copy-out");
     c->keys_pending = true;
     return VEST_OK;
 }
@@ -445,6 +491,11 @@ int vest_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
             return VEST_EINVAL;
         }
     CALL_HIP(c, launch_prune(c, core_k, factor_k), "prune");
+    if (c->padded) {
+        for (int n = 0; n < c->N; ++n)
+            if (factor_k[n] > 0) CALL_HIP(c, launch_pad_out_factor(c, n), "padded copy-out");
+        CALL_HIP(c, launch_pad_out_masks(c), "padded copy-out");
+    }
     if (core_k > 0) {
         c->marked_core += core_k;
         c->core_version++;
@@ -514,6 +565,10 @@ int vest_normalize(vest_ctx *c)
     int rc = live(c);
     if (rc) return rc;
     CALL_HIP(c, launch_normalize(c), "normalisation");
+    if (c->padded) {
+        for (int n = 0; n < c->N; ++n) CALL_HIP(c, launch_pad_out_factor(c, n), "padded copy-out");
+        CALL_HIP(c, launch_pad_out_core(c), "padded copy-out");
+    }
     c->core_version++;
     for (int n = 0; n < c->N; ++n) c->ag_valid[n] = false;
     c->e_valid = false;
@@ -576,9 +631,16 @@ int vest_value_keys(vest_ctx *c, double *core_key, double *const *factor_key)
     if (!core_key || !factor_key) { set_error("null key pointer"); return VEST_EINVAL; }
     for (int n = 0; n < c->N; ++n)
         if (!factor_key[n]) { set_error("null factor key pointer (mode %d)", n); return VEST_EINVAL; }
-    CALL_HIP(c, launch_value_keys(c, core_key, factor_key), "value keys");
-    for (int n = 0; n < c->N; ++n) c->key_fac[n] = factor_key[n];
-    c->key_core = core_key;
+    if (c->padded) {
+        CALL_HIP(c, launch_value_keys(c, c->pkey_core, c->pkey_fac), "value keys");
+        CALL_HIP(c, launch_pad_out_keys(c, core_key, factor_key), "padded key copy-out");
+        for (int n = 0; n < c->N; ++n) c->key_fac[n] = c->pkey_fac[n];
+        c->key_core = c->pkey_core;
+    } else {
+        CALL_HIP(c, launch_value_keys(c, core_key, factor_key), "value keys");
+        for (int n = 0; n < c->N; ++n) c->key_fac[n] = factor_key[n];
+        c->key_core = core_key;
+    }
     c->keys_pending = true;
     return VEST_OK;
 }

@@ -29,13 +29,17 @@
 
 #include "vest.h"
 
-// (order, uniform rank) pairs with compiled kernel instances.
-#define VEST_SHAPES(X) X(2, 2) X(2, 3) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 8) X(3, 10) \
-    X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 8) X(5, 3) X(6, 3) X(7, 3) X(8, 3) X(9, 3) X(10, 3)
+// (order, uniform rank) pairs with compiled kernel instances.  A context with
+// unequal per-mode ranks runs the instance of its largest rank (pad.hip).
+#define VEST_SHAPES(X) X(2, 2) X(2, 3) X(3, 2) X(3, 3) X(3, 4) X(3, 5) X(3, 6) X(3, 7) X(3, 8) X(3, 9) \
+    X(3, 10) X(4, 2) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(4, 7) X(4, 8) X(4, 9) X(4, 10) X(5, 3) X(6, 3) X(7, 3)   \
+    X(8, 3) X(9, 3) X(10, 3)
 
-// The dense contraction of Eq. 11 is unrolled per (N, J); from order 8 it is
-// not instantiated and every factor pass runs the looped gather form.
-__host__ __device__ constexpr bool dense_form(int N, int J) { return N <= 7 && J > 0; }
+// The dense contraction of Eq. 11 is unrolled per (N, J) up to 4096 core
+// elements (order 4 at rank 8, order 7 at rank 3); beyond, every factor pass
+// runs the looped gather form.
+__host__ __device__ constexpr int dense_pow(int b, int e) { return e == 0 ? 1 : b * dense_pow(b, e - 1); }
+__host__ __device__ constexpr bool dense_form(int N, int J) { return J > 0 && dense_pow(J, N) <= 4096; }
 
 namespace vest {
 
@@ -158,11 +162,28 @@ struct vest_ctx {
     bool f32 = false;                 // compute type is float (FP32 and BF16 forms)
     int kernel_policy = 0;            // VEST_KERNEL_AUTO / _DENSE / _GATHER
 
-    // caller-owned model state
+    // model state the kernels work on: the caller's arrays, or, when the
+    // per-mode ranks differ, padded copies in the workspace (see `padded`)
     double *A[VEST_MAX_ORDER] = {};
     double *core = nullptr;
     uint32_t *fmask[VEST_MAX_ORDER] = {};
     uint8_t *cmask = nullptr;
+
+    // Unequal per-mode ranks J_n: the kernels run on the uniform rank
+    // J = max J_n with every element outside the caller's J_1 x .. x J_N
+    // model marked (pruned, value 0) in workspace copies of the factors,
+    // core and marking tables.  Marked elements are zero and never updated,
+    // so the padded model is the caller's model exactly; every call that
+    // changes the state copies the caller's part back (pad.hip).
+    bool padded = false;
+    int32_t uranks[VEST_MAX_ORDER] = {};
+    int64_t uG = 0;                   // prod J_n of the caller's core
+    double *uA[VEST_MAX_ORDER] = {};
+    double *ucore = nullptr;
+    uint32_t *ufmask[VEST_MAX_ORDER] = {};
+    uint8_t *ucmask = nullptr;
+    double *pkey_core = nullptr;      // padded keys (the ones vest_prune reads)
+    double *pkey_fac[VEST_MAX_ORDER] = {};
 
     // workspace-resident derived state
     vest::ModeLayout lay[VEST_MAX_ORDER];
@@ -245,6 +266,12 @@ hipError_t launch_sumsq(hipStream_t s, const double *v, int64_t n, double *parti
 hipError_t launch_mask_init(vest_ctx *c, int64_t *counts_dev);
 hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, char *scratch,
                          size_t scratch_bytes, int *bad);
+// padded contexts (pad.hip): caller arrays -> workspace copies, and back
+hipError_t launch_pad_in(vest_ctx *c);
+hipError_t launch_pad_out_factor(vest_ctx *c, int mode);
+hipError_t launch_pad_out_core(vest_ctx *c);
+hipError_t launch_pad_out_masks(vest_ctx *c);
+hipError_t launch_pad_out_keys(vest_ctx *c, double *core_key, double *const *factor_key);
 
 // ---------------------------------------------------------------- workspace
 struct Plan {
@@ -274,5 +301,6 @@ struct Bump {
 
 void set_error(const char *fmt, ...);
 int check_desc(const vest_desc *d);   // VEST_OK or the code vest_init would return for the descriptor
+int max_rank(const vest_desc *d);     // the uniform rank the kernels of a context run at
 
 }  // namespace vest
