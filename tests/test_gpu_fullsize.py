@@ -1,0 +1,136 @@
+"""GPU parity at the benchmark's full size and over long runs, against
+expected values the FP64 oracle wrote (tests/golden/make_golden.py, which
+calls only the oracle and the seeded input generator).
+
+* config2-full: the 10^7-entry planted workload over (10^5)^3, ranks 10^3,
+  launched as the benchmark launches it (FP64, default kernel policy): one
+  Alg. 2 iteration, loss terms, the whole core and sampled factor rows;
+  responsibility keys (whole core, sampled factor rows); one prune step at
+  pr_1 = 0.01, the newly marked elements of every tensor identical; loss
+  after the prune.
+* config2-1e6: the same recipe at 10^6 entries over (10^4)^3, 20 iterations:
+  loss after every iteration, the core after the first and the last, sampled
+  rows after the last.
+* config4-auto: the order-4 Zipf workload 50k x 50k x 1000 x 24, ranks 8^4,
+  at 10^6 entries under VeST^auto (elbow rule, cap 0.95) through the host
+  schedule with compaction and the final normalisation: RE and prune decision
+  of every iteration, final core, core mask, factor masks (digest and count),
+  sampled rows.
+
+Bar: the FP64 bar of test_gpu_parity (element-wise 1e-10 relative above a
+floor of 1e-4 of each tensor's largest magnitude; loss terms 1e-10 relative;
+masks identical).
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1904_02603_amd import synth
+from test_gpu_parity import RTOL, V, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+LOSS_KEYS = ["sse", "xnorm2", "reg", "loss", "re"]
+
+
+def golden(case):
+    path = os.path.join(GOLDEN, case + ".npz")
+    if not os.path.exists(path):
+        pytest.skip("expected values not generated: python tests/golden/make_golden.py " + case)
+    return np.load(path)
+
+
+def check_loss(L, ref, what):
+    for k, r in zip(LOSS_KEYS, ref):
+        assert abs(L[k] - r) <= RTOL * abs(r), (what, k, L[k], r)
+
+
+def check(got, ref, what):
+    e = rel_err(got, ref)
+    say("  %s: element-wise rel err %.2e" % (what, e))
+    assert e <= RTOL, (what, e)
+
+
+def check_rows(ctx, g, what):
+    for n in range(ctx.N):
+        rows = torch.as_tensor(g["rows_m%d" % n], device="cuda")
+        check(ctx.factors[n][rows], g["vals_m%d" % n], "%s rows of mode %d" % (what, n))
+
+
+def test_config2_full_size_iteration_keys_and_prune():
+    g = golden("config2-full")
+    v = V()
+    p = synth.workload("planted-1e5^3-nnz1e7-r10")
+    ctx = v.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"])
+    del p
+    ctx.iteration()
+    check_loss(ctx.loss(), g["loss_it1"], "iteration 1")
+    check(ctx.core, g["core_it1"], "core")
+    check_rows(ctx, g, "iteration 1")
+    ck, fk = ctx.responsibility()
+    check(ck, g["core_key"], "core keys")
+    for n in range(3):
+        rows = torch.as_tensor(g["rows_m%d" % n], device="cuda")
+        check(fk[n][rows], g["keys_m%d" % n], "keys of mode %d" % n)
+    cm0 = ctx.cmask.bool().clone()
+    fm0 = [m.clone() for m in ctx.factor_masks_bool()]
+    k = [int(x) for x in g["prune_counts"]]
+    ctx.prune(k[0], k[1:])
+    torch.cuda.synchronize()
+    new_c = torch.nonzero((ctx.cmask.bool() & ~cm0).flatten()).flatten().cpu().numpy()
+    assert np.array_equal(new_c, g["pruned_core"]), "core prune set"
+    for n, (m, m0) in enumerate(zip(ctx.factor_masks_bool(), fm0)):
+        new = torch.nonzero((m & ~m0).flatten()).flatten().cpu().numpy()
+        say("  mode %d: %d pruned" % (n, new.size))
+        assert np.array_equal(new, g["pruned_m%d" % n]), "prune set of mode %d" % n
+    check_loss(ctx.loss(), g["loss_after_prune"], "after prune")
+    ctx.close()
+
+
+def test_config2_1e6_twenty_iterations():
+    g = golden("config2-1e6")
+    v = V()
+    p = synth.workload("planted-1e5^3-nnz1e7-r10", nnz=10 ** 6, dims=(10 ** 4,) * 3)
+    ctx = v.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"])
+    ref = g["loss_per_iteration"]
+    for it in range(ref.shape[0]):
+        ctx.iteration()
+        L = ctx.loss()
+        say("  iteration %d: RE %.12f (oracle %.12f)" % (it + 1, L["re"], ref[it][4]))
+        check_loss(L, ref[it], "iteration %d" % (it + 1))
+        if it == 0:
+            check(ctx.core, g["core_it1"], "core after iteration 1")
+    check(ctx.core, g["core_final"], "core after the last iteration")
+    check_rows(ctx, g, "last iteration")
+    ctx.close()
+
+
+def test_config4_shape_vest_auto():
+    g = golden("config4-auto")
+    v = V()
+    from paper_1904_02603_amd.schedule import PruneSchedule, run
+    p = synth.workload("planted-zipf-50k.50k.1k.24-nnz5e7-r8", nnz=10 ** 6)
+    ctx = v.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=p["reg"], lam=p["lam"])
+    steps = g["steps"]
+    log = []
+    run(ctx, int(steps.shape[0]), PruneSchedule(mode="auto", target=0.95), log=log.append, compact_every=5,
+        normalize=True)
+    for rec, ref in zip(log, steps):
+        say("  t %d: RE %.12f (oracle %.12f), pruned %s (oracle %d)" % (rec["iter"], rec["re"], ref[1],
+                                                                          rec["pruned"], int(ref[3])))
+        assert abs(rec["re"] - ref[1]) <= RTOL * ref[1], rec
+        assert rec["pruned"] == bool(ref[3]), rec
+    assert len(log) == steps.shape[0]
+    check_loss(ctx.loss(), g["loss_final"], "final")
+    check(ctx.core, g["core_final"], "final core")
+    assert np.array_equal(ctx.cmask.cpu().numpy(), g["core_mask"]), "core mask"
+    for n, m in enumerate(ctx.factor_masks_bool()):
+        b = np.ascontiguousarray(m.cpu().numpy().astype(np.uint8))
+        assert int(b.sum()) == int(g["mask_count"][n]), ("mask count", n)
+        assert hashlib.sha256(b.tobytes()).hexdigest() == str(g["mask_digest"][n]), ("mask", n)
+    check_rows(ctx, g, "final")
+    ctx.close()
