@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 
 #include "device.h"
 #include "internal.h"
@@ -339,7 +340,7 @@ __global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, i
     out[q] = (T)A[i * J + j];
 }
 
-// Partial product of kGramRows rows on the FP64 matrix cores:
+// Partial product of `rows` rows (a multiple of 32) on the FP64 matrix cores:
 // part[b] = sum_r rb_r^T kp_r (W1 x W2).  Wave ti of the block owns the
 // 16-row band ti of the output and every 16 x 16 tile along it; one
 // v_mfma_f64_16x16x4 step consumes four rows r: lane l supplies
@@ -351,7 +352,7 @@ __global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, i
 template <int W1, int W2>
 __global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__restrict__ rb, int ldrb,
                                                                  const double *__restrict__ kp, int ldkp,
-                                                                 int64_t nrows, double *__restrict__ part)
+                                                                 int64_t nrows, int rows, double *__restrict__ part)
 {
     constexpr int T1 = (W1 + 15) / 16, T2 = (W2 + 15) / 16;
     constexpr int SUB = 32, W2P = 16 * T2, NT = 64 * T1;
@@ -359,12 +360,12 @@ __global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__
     static_assert(kGramRows % SUB == 0, "sub-blocks of 32 rows");
     __shared__ double skp[SUB * W2P];
     const int lane = threadIdx.x & (kWave - 1), ti = threadIdx.x / kWave;
-    const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
     const int ci = 16 * ti + (lane & 15);
     f64x4 acc[T2];
 #pragma unroll
     for (int tj = 0; tj < T2; ++tj) acc[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int s0 = 0; s0 < kGramRows; s0 += SUB) {
+    for (int s0 = 0; s0 < rows; s0 += SUB) {
         double v[PER];
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -409,6 +410,20 @@ __global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__
 
 template <int W1>
 constexpr int gram_threads() { return 64 * ((W1 + 15) / 16); }
+
+// Rows per gram partial: the smallest multiple of kGramRows that keeps the
+// launch at about two waves per SIMD (1024 SIMDs); fewer, longer partials
+// also shorten the fixed-order sum.  The workspace holds partials for
+// kGramRows, so any larger choice fits.
+template <int W1>
+static int gram_rows(int64_t nrows)
+{
+    const int T1 = (W1 + 15) / 16;
+    int rows = kGramRows;
+    while (rows < 4096 && ((nrows + rows - 1) / rows) * T1 > 2048) rows *= 2;
+    if (const char *e = getenv("VEST_GRAM_ROWS")) rows = atoi(e);
+    return rows;
+}
 
 // Fixed-order sum of the gram partials: block b owns outputs 64 b .. 64 b + 63;
 // wave w of the block sums partials w, w + 16, ... (coalesced across lanes),
@@ -632,7 +647,8 @@ static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out,
     const ModeLayout &L = c->lay[N - 1];
     const int64_t Ilast = c->d.dims[N - 1];
     const int blocks = (L.nwaves + 3) / 4;
-    const int64_t gchunks = (Ilast + kGramRows - 1) / kGramRows;
+    const int grows = gram_rows<W1>(Ilast);
+    const int64_t gchunks = (Ilast + grows - 1) / grows;
     const int nslab = ipow(J, N - 2);
     hipLaunchKernelGGL(k_kp2<J>, dim3((unsigned)((Ilast + 255) / 256)), dim3(256), 0, st, c->A[N - 1], Ilast, W2, c->kp);
     for (int s0 = 0; s0 < nslab; s0 += SB) {
@@ -650,7 +666,7 @@ static void core_keys_batches(vest_ctx *c, SlabArgs<N, J, T> a, double *key_out,
             hipLaunchKernelGGL(k_slab_long<PER * SB>, dim3(L.nlong), dim3(64), 0, st, a.partials, L.longrows,
                                c->rowbuf, c->ldrb);
         hipLaunchKernelGGL((k_gram<W1, W2>), dim3((unsigned)gchunks), dim3(gram_threads<W1>()), 0, st, c->rowbuf, c->ldrb, c->kp, W2,
-                           Ilast, c->gram_part);
+                           Ilast, grows, c->gram_part);
         hipLaunchKernelGGL(k_gramsum, dim3((W1 * W2 + 63) / 64), dim3(1024), 0, st, c->gram_part, gchunks, W1 * W2,
                            c->gram);
         const int64_t base = (int64_t)s0 * J * J;
@@ -690,7 +706,8 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
     a.partials = partials;
 
     const int blocks = (L.nwaves + 3) / 4;
-    const int64_t gchunks = (Ilast + kGramRows - 1) / kGramRows;
+    const int grows = gram_rows<GW>(Ilast);
+    const int64_t gchunks = (Ilast + grows - 1) / grows;
     const int nslab = ipow(J, N - 2);
     auto digits = [&](int s, int32_t *out) {
         for (int m = N - 3; m >= 0; --m) {
@@ -722,7 +739,7 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
             hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, partials, L.longrows,
                                c->rowbuf, c->ldrb);
         hipLaunchKernelGGL((k_gram<GW, GW>), dim3((unsigned)gchunks), dim3(gram_threads<GW>()), 0, st, c->rowbuf, c->ldrb, c->kp, GW,
-                           Ilast, c->gram_part);
+                           Ilast, grows, c->gram_part);
         hipLaunchKernelGGL(k_gramsum, dim3((GW * GW + 63) / 64), dim3(1024), 0, st, c->gram_part, gchunks, GW * GW,
                            c->gram);
         const int64_t base = (int64_t)s * J * J;

@@ -82,11 +82,22 @@ __global__ void __launch_bounds__(256) k_mode_key(const int32_t *__restrict__ id
     }
 }
 
-__global__ void __launch_bounds__(256) k_hist(const uint32_t *__restrict__ keys, int64_t nnz,
-                                              uint32_t *__restrict__ counts)
+// Row lengths from the sorted row keys: every run of equal keys is one row.
+// The first entry of a run records where it starts, the last one (after a
+// kernel boundary) the length; no atomics, so rows of millions of entries (a
+// Zipf-skewed mode) cost no more than short ones.
+__global__ void __launch_bounds__(256) k_run_start(const uint32_t *__restrict__ keys, int64_t nnz,
+                                                   uint32_t *__restrict__ start)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nnz) atomicAdd(&counts[keys[q]], 1u);
+    if (q < nnz && (q == 0 || keys[q] != keys[q - 1])) start[keys[q]] = (uint32_t)q;
+}
+
+__global__ void __launch_bounds__(256) k_run_len(const uint32_t *__restrict__ keys, int64_t nnz,
+                                                 const uint32_t *__restrict__ start, uint32_t *__restrict__ counts)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz && (q == nnz - 1 || keys[q] != keys[q + 1])) counts[keys[q]] = (uint32_t)(q + 1) - start[keys[q]];
 }
 
 template <typename T>
@@ -271,7 +282,10 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
         size_t tb = c->sort_tmp_bytes;
         CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(c->sort_tmp, tb, ka, kb, va, vb, (int)nnz, 0, bits_for(I), st));
         CHECK_HIP(hipMemsetAsync(counts, 0, I * 4, st));
-        hipLaunchKernelGGL(k_hist, dim3(grid_for(nnz)), dim3(256), 0, st, kb, nnz, counts);
+        // run starts go to the row-placement buffer, which is written only later
+        auto *start = reinterpret_cast<uint32_t *>(place);
+        hipLaunchKernelGGL(k_run_start, dim3(grid_for(nnz)), dim3(256), 0, st, kb, nnz, start);
+        hipLaunchKernelGGL(k_run_len, dim3(grid_for(nnz)), dim3(256), 0, st, kb, nnz, start, counts);
         cnt.assign(I, 0);
         CHECK_HIP(hipMemcpyAsync(cnt.data(), counts, I * 4, hipMemcpyDeviceToHost, st));
         CHECK_HIP(hipStreamSynchronize(st));
