@@ -23,7 +23,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <cstdlib>
 
 #include "device.h"
 #include "internal.h"
@@ -421,7 +420,6 @@ static int gram_rows(int64_t nrows)
     const int T1 = (W1 + 15) / 16;
     int rows = kGramRows;
     while (rows < 4096 && ((nrows + rows - 1) / rows) * T1 > 2048) rows *= 2;
-    if (const char *e = getenv("VEST_GRAM_ROWS")) rows = atoi(e);
     return rows;
 }
 
