@@ -7,10 +7,15 @@
  * in arrival order, later jobs filling in when the head of the queue does not
  * fit, as soon as a slot is free and the job's device footprint (observed
  * tensor, model state, marking tables and the vest_init workspace) fits in
- * the free part of the arena.  An admitted job keeps its state resident; the
- * loop enqueues one iteration of Alg. 2 (every factor sweep, Alg. 4, then the
- * core sweep, Eq. 12 / Eq. 14) at a time on the job's stream, so the work of
- * all admitted jobs overlaps on the device.  A finished job's factors, core
+ * the free part of the arena.  An admitted job keeps its state resident.
+ * Admitted jobs of one class -- same order, rank and precision, entry counts
+ * within a factor of 4 -- advance together:
+ * the loop enqueues one batched iteration of Alg. 2 (every factor sweep,
+ * Alg. 4, then the core sweep, Eq. 12 / Eq. 14; vest_iterate_many) for all
+ * idle jobs of the class on the class's stream, every kernel of it launched
+ * once for the whole class; classes run on separate streams, so the work of
+ * all admitted jobs overlaps on the device.  A job the batched path does not
+ * take (unequal ranks) runs its iterations alone on its slot's stream.  A finished job's factors, core
  * and loss (Eq. 1 / Eq. 2, Eq. 4) are copied to host memory owned by the
  * server and its device memory returns to the arena.  Every kernel of the
  * library sums in a fixed order, so a job's result does not depend on what
@@ -44,6 +49,28 @@ typedef struct {
     int32_t reserved;               /* must be 0                                  */
 } vest_job;
 
+/* One iteration of Alg. 2 (the factor sweep of every mode, Alg. 4, then the
+ * core sweep, Eq. 12 / Eq. 14) for n contexts of one shape -- same order,
+ * rank and precision -- in one sequence of launches: every kernel of the
+ * iteration runs once for all the contexts, its launch carrying a table of
+ * per-context tasks that a grid-stride loop walks (virtual block b of the
+ * launch is a block of one context's work).  Each context's arithmetic is the
+ * same as vest_sweep_factor / vest_sweep_core run on it alone, so its results
+ * do not depend on the batch it runs in.
+ *   ctxs         host array of n distinct contexts
+ *   stream       hipStream_t all launches go to; the caller orders the
+ *                contexts' own earlier work before it
+ *   dev_table    device buffer of table_bytes for the task tables
+ *   host_table   host staging of table_bytes (pinned memory recommended);
+ *                it is copied to dev_table on `stream` and must not be
+ *                modified until that copy has completed
+ * VEST_EUNSUPPORTED, with nothing enqueued, when a context does not fit the
+ * batched path (unequal ranks, marks that make a factor pass take the gather
+ * contraction, instrumentation on, a different shape) or the tables exceed
+ * table_bytes; the caller then runs the contexts one by one. */
+int vest_iterate_many(vest_ctx *const *ctxs, int32_t n, void *stream, void *dev_table, void *host_table,
+                      size_t table_bytes);
+
 /* Create a server with an arena of device_bytes (allocated once, on the
  * current device) and `slots` concurrent jobs (1..256). */
 int vest_server_create(size_t device_bytes, int32_t slots, vest_server **out /* host out */);
@@ -72,8 +99,9 @@ int vest_server_status(vest_server *s, int64_t id, int32_t *state, int32_t *erro
 int vest_server_fetch(vest_server *s, int64_t id, double *const *factors, double *core, double *loss);
 
 /* out[0] queued, out[1] active, out[2] finished (not fetched), out[3] arena
- * bytes in use, out[4] arena size, out[5] largest free block. */
-int vest_server_stats(vest_server *s, int64_t *out /* 6 values */);
+ * bytes in use, out[4] arena size, out[5] largest free block, out[6] batched
+ * iterations issued, out[7] job-iterations they carried. */
+int vest_server_stats(vest_server *s, int64_t *out /* 8 values */);
 
 /* Wait for all enqueued work and release everything (unfetched results too). */
 int vest_server_destroy(vest_server *s);

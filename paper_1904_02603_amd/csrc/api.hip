@@ -432,6 +432,61 @@ int vest_sweep_core(vest_ctx *c)
     return refresh_gp(c);
 }
 
+int vest_iterate_many(vest_ctx *const *cs, int32_t n, void *stream, void *dev_table, void *host_table,
+                      size_t table_bytes)
+{
+    if (!cs || n < 1 || !dev_table || !host_table) { set_error("bad batch arguments"); return VEST_EINVAL; }
+    for (int i = 0; i < n; ++i) {
+        int rc = live(cs[i]);
+        if (rc) return rc;
+    }
+    const vest_ctx *c0 = cs[0];
+    for (int i = 0; i < n; ++i) {
+        const vest_ctx *c = cs[i];
+        bool fits = c->N == c0->N && c->J == c0->J && c->f32 == c0->f32 && c->d.precision == c0->d.precision &&
+                    !c->padded && !c->slab_ev && batch_dense_ok(c) && resid_fuses_slab0(c);
+        for (int m = 0; m < c->N && fits; ++m) fits = c->ag_valid[m] && c->gp_version[m] == c->core_version;
+        for (int j = 0; j < i && fits; ++j) fits = cs[j] != c;
+        if (!fits) {
+            set_error("context %d does not fit the batched path (shape, form, marks or state)", i);
+            return VEST_EUNSUPPORTED;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    BatchArena ba;
+    ba.host = (char *)host_table;
+    ba.dev = (char *)dev_table;
+    ba.cap = table_bytes;
+    LaunchList L;
+    bool ok = true;
+    for (int m = 0; m < c0->N && ok; ++m) ok = plan_factor_batch(cs, n, m, OP_SWEEP, st, ba, L);
+    ok = ok && plan_factor_batch(cs, n, c0->N - 1, OP_RESID_S0, st, ba, L);
+    ok = ok && plan_core_batch(cs, n, true, st, ba, L);
+    ok = ok && plan_permute_batch(cs, n, st, ba, L);
+    if (!ok) {
+        set_error("batch tables exceed %zu bytes or the shape has no batched path", table_bytes);
+        return VEST_EUNSUPPORTED;
+    }
+    hipError_t e = hipMemcpyAsync(dev_table, host_table, ba.used, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        for (auto &f : L) f();
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        for (int i = 0; i < n; ++i) cs[i]->dead = true;
+        return device_error(nullptr, e, "batched iteration");
+    }
+    for (int i = 0; i < n; ++i) {
+        vest_ctx *c = cs[i];
+        c->core_version++;
+        for (int m = 0; m < c->N; ++m) c->gp_version[m] = c->core_version;
+        c->e_valid = true;
+        c->ms_valid = true;
+        c->hdiag_valid = true;
+    }
+    return VEST_OK;
+}
+
 int vest_responsibility(vest_ctx *c, double *core_key, double *const *factor_key)
 {
     int rc = live(c);
@@ -735,7 +790,7 @@ int vest_destroy(vest_ctx *c)
         (void)hipEventDestroy(c->join);
     }
     if (c->slab_ev) drop_slab_events(c);
-    if (c->host_red) (void)hipHostFree(c->host_red);
+    if (c->host_red && c->host_red_owned) (void)hipHostFree(c->host_red);
     delete c;
     if (e != hipSuccess) return device_error(nullptr, e, "destroy");
     return VEST_OK;

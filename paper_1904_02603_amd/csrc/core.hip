@@ -64,13 +64,13 @@ template <typename T>
 __host__ __device__ constexpr int slab_u() { return sizeof(T) == 4 ? 4 : 2; }
 
 template <int N, int J, typename T, bool ACC>
-__global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
+__device__ __forceinline__ void slab_body(const SlabArgs<N, J, T> &a, int bx)
 {
     constexpr int NA = nacc_vc(J);
     constexpr int U = slab_u<T>();
     constexpr int NI = N > 2 ? N - 2 : 1;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int wave = bx * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (wave >= a.nwaves) return;
     const WaveInfo wi = a.waves[wave];
     const int grp = lane >> wi.glog;
@@ -176,6 +176,25 @@ __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 #pragma unroll
             for (int v = 0; v < NA; ++v) dst[v] = (double)s[v];
         }
+    }
+}
+
+template <int N, int J, typename T, bool ACC>
+__global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
+{
+    slab_body<N, J, T, ACC>(a, blockIdx.x);
+}
+
+// Several contexts of one shape in one launch (virtual block b - off[t] of
+// task t; see k_rowgroup_multi).
+template <int N, int J, typename T, bool ACC>
+__global__ void __launch_bounds__(256) k_slab_multi(const SlabArgs<N, J, T> *__restrict__ tab,
+                                                    const int32_t *__restrict__ off, int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const SlabArgs<N, J, T> a = tab[t];   // arguments in registers, read once
+        slab_body<N, J, T, ACC>(a, b - off[t]);
     }
 }
 
@@ -286,20 +305,46 @@ __global__ void __launch_bounds__(256) k_slabkeys(SlabArgs<N, J, T> a, int nsb)
 }
 
 template <int NA>
-__global__ void __launch_bounds__(64) k_slab_long(const double *__restrict__ part, const LongRow *__restrict__ lr,
-                                                  double *__restrict__ rowbuf, int ldrb)
+__device__ __forceinline__ void slab_long_body(const double *__restrict__ part, const LongRow *__restrict__ lr,
+                                               double *__restrict__ rowbuf, int ldrb, int bx)
 {
     __shared__ double sh[NA];
-    const LongRow L = lr[blockIdx.x];
+    const LongRow L = lr[bx];
     sum_partials<NA>(part, L, sh, threadIdx.x);
     for (int v = threadIdx.x; v < NA; v += 64) rowbuf[(int64_t)L.row * ldrb + v] = sh[v];
 }
 
+template <int NA>
+__global__ void __launch_bounds__(64) k_slab_long(const double *__restrict__ part, const LongRow *__restrict__ lr,
+                                                  double *__restrict__ rowbuf, int ldrb)
+{
+    slab_long_body<NA>(part, lr, rowbuf, ldrb, blockIdx.x);
+}
+
+struct SlabLongTask {
+    const double *part;
+    const LongRow *lr;
+    double *rowbuf;
+    int32_t ldrb;
+};
+
+template <int NA>
+__global__ void __launch_bounds__(64) k_slab_long_multi(const SlabLongTask *__restrict__ tab,
+                                                        const int32_t *__restrict__ off, int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const SlabLongTask tk = tab[t];
+        slab_long_body<NA>(tk.part, tk.lr, tk.rowbuf, tk.ldrb, b - off[t]);
+        __syncthreads();   // the LDS sums are reused by the next long row
+    }
+}
+
 // kp row r = [a_r (J) | packed a_r a_r^T (J(J+1)/2) | 0 padding]
 template <int J>
-__global__ void __launch_bounds__(256) k_kp(const double *__restrict__ A, int64_t I, int gw, double *__restrict__ kp)
+__device__ __forceinline__ void kp_body(const double *__restrict__ A, int64_t I, int gw, double *__restrict__ kp, int bx)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = (int64_t)bx * blockDim.x + threadIdx.x;
     if (r >= I) return;
     double a[J];
     load_row<J, double>(A + r * J, a);
@@ -311,6 +356,30 @@ __global__ void __launch_bounds__(256) k_kp(const double *__restrict__ A, int64_
 #pragma unroll
         for (int v = t; v < J; ++v) d[J + sym<J>(t, v)] = a[t] * a[v];
     for (int v = nacc_vc(J); v < gw; ++v) d[v] = 0.0;
+}
+
+template <int J>
+__global__ void __launch_bounds__(256) k_kp(const double *__restrict__ A, int64_t I, int gw, double *__restrict__ kp)
+{
+    kp_body<J>(A, I, gw, kp, blockIdx.x);
+}
+
+struct KpTask {
+    const double *A;
+    int64_t I;
+    int32_t gw;
+    double *kp;
+};
+
+template <int J>
+__global__ void __launch_bounds__(256) k_kp_multi(const KpTask *__restrict__ tab, const int32_t *__restrict__ off,
+                                                  int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const KpTask tk = tab[t];
+        kp_body<J>(tk.A, tk.I, tk.gw, tk.kp, b - off[t]);
+    }
 }
 
 // kp2 row r = [a_r (J) | a_r^2 (J) | 0 padding]
@@ -331,12 +400,37 @@ __global__ void __launch_bounds__(256) k_kp2(const double *__restrict__ A, int64
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, int64_t I, int J, T *__restrict__ out)
+__device__ __forceinline__ void colcopy_body(const double *__restrict__ A, int64_t I, int J, T *__restrict__ out, int bx)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)bx * blockDim.x + threadIdx.x;
     if (q >= I * J) return;
     const int64_t j = q / I, i = q % I;
     out[q] = (T)A[i * J + j];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, int64_t I, int J, T *__restrict__ out)
+{
+    colcopy_body<T>(A, I, J, out, blockIdx.x);
+}
+
+template <typename T>
+struct ColTask {
+    const double *A;
+    int64_t I;
+    int32_t J;
+    T *out;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_colcopy_multi(const ColTask<T> *__restrict__ tab,
+                                                       const int32_t *__restrict__ off, int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const ColTask<T> tk = tab[t];
+        colcopy_body<T>(tk.A, tk.I, tk.J, tk.out, b - off[t]);
+    }
 }
 
 // Partial product of `rows` rows (a multiple of 32) on the FP64 matrix cores:
@@ -349,9 +443,8 @@ __global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, i
 // every wave, are staged in LDS 32 at a time; columns past W1 / W2 and rows
 // past nrows enter as zeros.
 template <int W1, int W2>
-__global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__restrict__ rb, int ldrb,
-                                                                 const double *__restrict__ kp, int ldkp,
-                                                                 int64_t nrows, int rows, double *__restrict__ part)
+__device__ __forceinline__ void gram_body(const double *__restrict__ rb, int ldrb, const double *__restrict__ kp,
+                                          int ldkp, int64_t nrows, int rows, double *__restrict__ part, int bx)
 {
     constexpr int T1 = (W1 + 15) / 16, T2 = (W2 + 15) / 16;
     constexpr int SUB = 32, W2P = 16 * T2, NT = 64 * T1;
@@ -359,7 +452,7 @@ __global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__
     static_assert(kGramRows % SUB == 0, "sub-blocks of 32 rows");
     __shared__ double skp[SUB * W2P];
     const int lane = threadIdx.x & (kWave - 1), ti = threadIdx.x / kWave;
-    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const int64_t r0 = (int64_t)bx * rows;
     const int ci = 16 * ti + (lane & 15);
     f64x4 acc[T2];
 #pragma unroll
@@ -395,7 +488,7 @@ __global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__
                                                               0, 0);
         }
     }
-    double *o = part + (int64_t)blockIdx.x * W1 * W2;
+    double *o = part + (int64_t)bx * W1 * W2;
 #pragma unroll
     for (int tj = 0; tj < T2; ++tj) {
         const int j = 16 * tj + (lane & 15);
@@ -404,6 +497,35 @@ __global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__
             const int i = 16 * ti + 4 * q + (lane >> 4);
             if (i < W1 && j < W2) o[i * W2 + j] = acc[tj][q];
         }
+    }
+}
+
+template <int W1, int W2>
+__global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram(const double *__restrict__ rb, int ldrb,
+                                                                 const double *__restrict__ kp, int ldkp,
+                                                                 int64_t nrows, int rows, double *__restrict__ part)
+{
+    gram_body<W1, W2>(rb, ldrb, kp, ldkp, nrows, rows, part, blockIdx.x);
+}
+
+struct GramTask {
+    const double *rb;
+    const double *kp;
+    double *part;
+    int64_t nrows;
+    int32_t ldrb, ldkp, rows;
+};
+
+template <int W1, int W2>
+__global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram_multi(const GramTask *__restrict__ tab,
+                                                                       const int32_t *__restrict__ off, int ntask,
+                                                                       int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const GramTask tk = tab[t];
+        gram_body<W1, W2>(tk.rb, tk.ldrb, tk.kp, tk.ldkp, tk.nrows, tk.rows, tk.part, b - off[t]);
+        __syncthreads();   // the staged rows in LDS are reused by the next partial
     }
 }
 
@@ -426,12 +548,12 @@ static int gram_rows(int64_t nrows)
 // Fixed-order sum of the gram partials: block b owns outputs 64 b .. 64 b + 63;
 // wave w of the block sums partials w, w + 16, ... (coalesced across lanes),
 // then the 16 wave sums are added in wave order.
-__global__ void __launch_bounds__(1024) k_gramsum(const double *__restrict__ part, int64_t nparts, int n,
-                                                  double *__restrict__ out)
+__device__ __forceinline__ void gramsum_body(const double *__restrict__ part, int64_t nparts, int n,
+                                             double *__restrict__ out, int bx)
 {
     __shared__ double sh[16][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int q = blockIdx.x * 64 + lane;
+    const int q = bx * 64 + lane;
     double s0 = 0.0, s1 = 0.0;
     if (q < n) {
         int64_t c = w;
@@ -447,6 +569,30 @@ __global__ void __launch_bounds__(1024) k_gramsum(const double *__restrict__ par
         double t = 0.0;
         for (int i = 0; i < 16; ++i) t += sh[i][lane];
         out[q] = t;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_gramsum(const double *__restrict__ part, int64_t nparts, int n,
+                                                  double *__restrict__ out)
+{
+    gramsum_body(part, nparts, n, out, blockIdx.x);
+}
+
+struct GsumTask {
+    const double *part;
+    int64_t nparts;
+    int32_t n;
+    double *out;
+};
+
+__global__ void __launch_bounds__(1024) k_gramsum_multi(const GsumTask *__restrict__ tab,
+                                                        const int32_t *__restrict__ off, int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const GsumTask tk = tab[t];
+        gramsum_body(tk.part, tk.nparts, tk.n, tk.out, b - off[t]);
+        __syncthreads();   // the wave sums in LDS are reused by the next block of outputs
     }
 }
 
@@ -475,9 +621,9 @@ __device__ __forceinline__ double readlane_d(double v, int l)
 // denominator) are LDS broadcasts, and H lives in LDS.  The diagonal of H is
 // kept (it is sum w_q^2, reused by the core keys).
 template <int J>
-__global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gram, double *__restrict__ core,
-                                                  const uint8_t *__restrict__ cmask, int64_t base, double lambda,
-                                                  int reg, double *__restrict__ dprev, double *__restrict__ hdiag)
+__device__ __forceinline__ void slabsolve_body(const double *__restrict__ gram, double *__restrict__ core,
+                                               const uint8_t *__restrict__ cmask, int64_t base, double lambda,
+                                               int reg, double *__restrict__ dprev, double *__restrict__ hdiag)
 {
     constexpr int GW = gram_width(J);
     constexpr int B = J * J;
@@ -617,6 +763,36 @@ __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gra
     }
 }
 
+template <int J>
+__global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gram, double *__restrict__ core,
+                                                  const uint8_t *__restrict__ cmask, int64_t base, double lambda,
+                                                  int reg, double *__restrict__ dprev, double *__restrict__ hdiag)
+{
+    slabsolve_body<J>(gram, core, cmask, base, lambda, reg, dprev, hdiag);
+}
+
+struct SolveTask {
+    const double *gram;
+    double *core;
+    const uint8_t *cmask;
+    double *dprev;
+    double *hdiag;
+    int64_t base;
+    double lambda;
+    int32_t reg;
+};
+
+// one block per context
+template <int J>
+__global__ void __launch_bounds__(64) k_slabsolve_multi(const SolveTask *__restrict__ tab, int ntask)
+{
+    for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+        const SolveTask tk = tab[t];
+        slabsolve_body<J>(tk.gram, tk.core, tk.cmask, tk.base, tk.lambda, tk.reg, tk.dprev, tk.hdiag);
+        __syncthreads();   // LDS of the solve is reused by the next context
+    }
+}
+
 // Core keys of a batch of slabs: Delta(G_q) = 2 G_q sum e w_q + G_q^2 sum w_q^2 (Eq. 5).
 // sum w_q^2 comes from the batch product (WITH_D) or from the Gram diagonals
 // kept by the last core sweep.
@@ -749,6 +925,141 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
     digits(nslab - 1, a.lprev);
     if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, false>), dim3(blocks), dim3(256), 0, st, a);
     return hipGetLastError();
+}
+
+// The core sweep of several contexts of one shape, kernel by kernel as
+// core_pass_t launches it for one (slab passes, long-row sums, Gram product,
+// its sum and the sequential solve of every slab, then the last slab's
+// change applied to the residual), each launch carrying all the contexts.
+template <int N, int J, typename T>
+static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_t st, BatchArena &ba, LaunchList &L)
+{
+    const int last = N - 1;
+    constexpr int GW = gram_width(J);
+    const int nslab = ipow(J, N - 2);
+    std::vector<SlabArgs<N, J, T>> base(n);
+    std::vector<KpTask> kp(n);
+    std::vector<ColTask<T>> col;
+    std::vector<SlabLongTask> sl(n);
+    std::vector<GramTask> gr(n);
+    std::vector<GsumTask> gs(n);
+    std::vector<int32_t> kpoff(n + 1, 0), coloff(1, 0), soff(n + 1, 0), sloff(n + 1, 0), groff(n + 1, 0),
+        gsoff(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        vest_ctx *c = cs[i];
+        const ModeLayout &Ly = c->lay[last];
+        const int64_t Ilast = c->d.dims[last];
+        SlabArgs<N, J, T> &a = base[i];
+        a = SlabArgs<N, J, T>{};
+        a.waves = Ly.waves;
+        a.nwaves = Ly.nwaves;
+        a.row_order = Ly.row_order;
+        for (int m = 0; m < N - 1; ++m) a.oidx[m] = Ly.oidx[m];
+        for (int m = 0; m < N - 2; ++m) {
+            const int64_t I = c->d.dims[m];
+            col.push_back(ColTask<T>{c->A[m], I, J, reinterpret_cast<T *>(c->colA[m])});
+            coloff.push_back(coloff.back() + (int32_t)((I * J + 255) / 256));
+            a.colA[m] = reinterpret_cast<const T *>(c->colA[m]);
+            a.dimA[m] = I;
+        }
+        a.ms = reinterpret_cast<const T *>(c->ms);
+        for (int m = 0; m < N - 2; ++m) a.rowA[m] = reinterpret_cast<const T *>(c->Ag[m]);
+        a.Alast = reinterpret_cast<const T *>(c->Ag[last]);
+        a.e = reinterpret_cast<T *>(c->e);
+        a.dprev = c->dprev;
+        a.rowbuf = c->rowbuf;
+        a.ldrb = c->ldrb;
+        a.partials = c->partials;
+        kp[i] = KpTask{c->A[last], Ilast, GW, c->kp};
+        kpoff[i + 1] = kpoff[i] + (int32_t)((Ilast + 255) / 256);
+        soff[i + 1] = soff[i] + (Ly.nwaves + 3) / 4;
+        sl[i] = SlabLongTask{c->partials, Ly.longrows, c->rowbuf, c->ldrb};
+        sloff[i + 1] = sloff[i] + Ly.nlong;
+        const int grows = gram_rows<GW>(Ilast);
+        const int64_t gchunks = (Ilast + grows - 1) / grows;
+        gr[i] = GramTask{c->rowbuf, c->kp, c->gram_part, Ilast, c->ldrb, GW, grows};
+        groff[i + 1] = groff[i] + (int32_t)gchunks;
+        gs[i] = GsumTask{c->gram_part, gchunks, GW * GW, c->gram};
+        gsoff[i + 1] = gsoff[i] + (GW * GW + 63) / 64;
+    }
+    auto digits = [&](int s, int32_t *out) {
+        for (int m = N - 3; m >= 0; --m) {
+            out[m] = s % J;
+            s /= J;
+        }
+    };
+    // per-slab tables: the slab pass's arguments and the solve's tasks
+    std::vector<size_t> o_slab(nslab), o_solve(nslab);
+    std::vector<SlabArgs<N, J, T>> tab(n);
+    std::vector<SolveTask> sv(n);
+    for (int s = 0; s < nslab; ++s) {
+        for (int i = 0; i < n; ++i) {
+            tab[i] = base[i];
+            digits(s, tab[i].lead);
+            tab[i].has_prev = s > 0 ? 1 : 0;
+            if (s > 0) digits(s - 1, tab[i].lprev);
+            vest_ctx *c = cs[i];
+            sv[i] = SolveTask{c->gram, c->core, c->cmask, c->dprev, c->hdiag, (int64_t)s * J * J, c->d.lambda,
+                              c->d.reg};
+        }
+        o_slab[s] = ba.add(tab.data(), sizeof(SlabArgs<N, J, T>) * n);
+        o_solve[s] = ba.add(sv.data(), sizeof(SolveTask) * n);
+    }
+    for (int i = 0; i < n; ++i) {
+        tab[i] = base[i];
+        tab[i].has_prev = 1;
+        digits(nslab - 1, tab[i].lprev);
+    }
+    const size_t o_final = ba.add(tab.data(), sizeof(SlabArgs<N, J, T>) * n);
+    const size_t o_kp = ba.add(kp.data(), sizeof(KpTask) * n), o_kpoff = ba.add(kpoff.data(), 4 * (n + 1));
+    const size_t o_col = col.empty() ? 0 : ba.add(col.data(), sizeof(ColTask<T>) * col.size());
+    const size_t o_coloff = ba.add(coloff.data(), 4 * coloff.size());
+    const size_t o_soff = ba.add(soff.data(), 4 * (n + 1));
+    const size_t o_sl = ba.add(sl.data(), sizeof(SlabLongTask) * n), o_sloff = ba.add(sloff.data(), 4 * (n + 1));
+    const size_t o_gr = ba.add(gr.data(), sizeof(GramTask) * n), o_groff = ba.add(groff.data(), 4 * (n + 1));
+    const size_t o_gs = ba.add(gs.data(), sizeof(GsumTask) * n), o_gsoff = ba.add(gsoff.data(), 4 * (n + 1));
+    if (ba.overflow) return false;
+    const BatchArena B = ba;
+    const int ncol = (int)col.size();
+    const int tcol = coloff.back(), tkp = kpoff[n], tslab = soff[n], tsl = sloff[n], tgr = groff[n], tgs = gsoff[n];
+    auto grid = [](int total) { return total < kBatchGrid ? total : kBatchGrid; };
+    L.push_back([=]() {
+        if (tcol > 0)
+            hipLaunchKernelGGL(k_colcopy_multi<T>, dim3(grid(tcol)), dim3(256), 0, st, B.dptr<ColTask<T>>(o_col),
+                               B.dptr<int32_t>(o_coloff), ncol, tcol);
+        if (tkp > 0)
+            hipLaunchKernelGGL(k_kp_multi<J>, dim3(grid(tkp)), dim3(256), 0, st, B.dptr<KpTask>(o_kp),
+                               B.dptr<int32_t>(o_kpoff), n, tkp);
+        for (int s = 0; s < nslab; ++s) {
+            if (!(s == 0 && fused) && tslab > 0)
+                hipLaunchKernelGGL((k_slab_multi<N, J, T, true>), dim3(grid(tslab)), dim3(256), 0, st,
+                                   B.dptr<SlabArgs<N, J, T>>(o_slab[s]), B.dptr<int32_t>(o_soff), n, tslab);
+            if (tsl > 0)
+                hipLaunchKernelGGL(k_slab_long_multi<nacc_vc(J)>, dim3(grid(tsl)), dim3(64), 0, st,
+                                   B.dptr<SlabLongTask>(o_sl), B.dptr<int32_t>(o_sloff), n, tsl);
+            hipLaunchKernelGGL((k_gram_multi<GW, GW>), dim3(grid(tgr)), dim3(gram_threads<GW>()), 0, st,
+                               B.dptr<GramTask>(o_gr), B.dptr<int32_t>(o_groff), n, tgr);
+            hipLaunchKernelGGL(k_gramsum_multi, dim3(grid(tgs)), dim3(1024), 0, st, B.dptr<GsumTask>(o_gs),
+                               B.dptr<int32_t>(o_gsoff), n, tgs);
+            hipLaunchKernelGGL(k_slabsolve_multi<J>, dim3(grid(n)), dim3(64), 0, st, B.dptr<SolveTask>(o_solve[s]), n);
+        }
+        if (tslab > 0)
+            hipLaunchKernelGGL((k_slab_multi<N, J, T, false>), dim3(grid(tslab)), dim3(256), 0, st,
+                               B.dptr<SlabArgs<N, J, T>>(o_final), B.dptr<int32_t>(o_soff), n, tslab);
+    });
+    return true;
+}
+
+bool plan_core_batch(vest_ctx *const *cs, int n, bool fused, hipStream_t st, BatchArena &ba, LaunchList &L)
+{
+    const vest_ctx *c = cs[0];
+#define VEST_CASE(NN, JJ)                                                                    \
+    if (c->N == NN && c->J == JJ)                                                            \
+        return c->f32 ? plan_core_batch_t<NN, JJ, float>(cs, n, fused, st, ba, L)            \
+                      : plan_core_batch_t<NN, JJ, double>(cs, n, fused, st, ba, L);
+    VEST_SHAPES(VEST_CASE)
+#undef VEST_CASE
+    return false;
 }
 
 static hipError_t core_pass(vest_ctx *c, bool keys, double *key_out, bool slab0_done, hipStream_t st,

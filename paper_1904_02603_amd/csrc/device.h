@@ -226,6 +226,20 @@ __device__ __forceinline__ void delta_vec2(const CoreBases<T> &G, const T (&ra)[
     pair_all<N - 1, J, T>(G, ra, rb, buf, acca, accb, da, db, std::make_integer_sequence<int, ipow(J, N - 1)>{});
 }
 
+// Task of virtual block b in a launch that carries several contexts:
+// off[t] is the first virtual block of task t (off[0] = 0, nondecreasing);
+// the last task whose first block is <= b (tasks without blocks are skipped).
+__device__ __forceinline__ int task_of(const int32_t *__restrict__ off, int ntask, int b)
+{
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Slot-ordered copy of a per-entry factor row, interleaved per wave: the J
 // values of the 64 slots of one (wave, k) step form one contiguous block of
 // 64 J elements (slot bases are multiples of 64).  Inside the block, 8-byte

@@ -25,7 +25,10 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
+#include <functional>
 #include <type_traits>
+#include <vector>
 
 #include "vest.h"
 
@@ -211,6 +214,7 @@ struct vest_ctx {
     void *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
     double *host_red = nullptr;       // pinned host mirror of small results
+    bool host_red_owned = true;       // allocated by the context (else lent by a server)
 
     // bookkeeping
     double xnorm2 = 0.0;
@@ -272,6 +276,43 @@ hipError_t launch_pad_out_factor(vest_ctx *c, int mode);
 hipError_t launch_pad_out_core(vest_ctx *c);
 hipError_t launch_pad_out_masks(vest_ctx *c);
 hipError_t launch_pad_out_keys(vest_ctx *c, double *core_key, double *const *factor_key);
+
+// ------------------------------------------------------- batched contexts
+// One Alg. 2 iteration of several contexts of one shape (serving): every
+// kernel of the iteration runs once for all of them, its launch carrying a
+// table of per-context tasks (virtual blocks b - off[t] of task t).  The
+// tables are written to a host staging area, uploaded once, then the recorded
+// launches are issued.
+struct BatchArena {
+    char *host = nullptr;   // staging (pinned)
+    char *dev = nullptr;    // device mirror
+    size_t cap = 0, used = 0;
+    bool overflow = false;
+    size_t add(const void *p, size_t n)
+    {
+        const size_t o = (used + 255) & ~size_t(255);
+        if (o + n > cap) {
+            overflow = true;
+            return 0;
+        }
+        std::memcpy(host + o, p, n);
+        used = o + n;
+        return o;
+    }
+    template <class X>
+    X *dptr(size_t off) const { return reinterpret_cast<X *>(dev + off); }
+};
+using LaunchList = std::vector<std::function<void()>>;
+constexpr int kBatchGrid = 2048;      // blocks of a multi-context launch (grid-stride over tasks)
+
+// Factor pass (OP_SWEEP with its long-row finish, or OP_RESID_S0) of mode
+// `mode` for every context; core sweep with the first slab's sums taken from
+// OP_RESID_S0 when `fused`; permuted cores of every mode.  false if a context
+// does not fit the batched (dense-contraction) path.
+bool plan_factor_batch(vest_ctx *const *cs, int n, int mode, int op, hipStream_t st, BatchArena &ba, LaunchList &L);
+bool plan_core_batch(vest_ctx *const *cs, int n, bool fused, hipStream_t st, BatchArena &ba, LaunchList &L);
+bool plan_permute_batch(vest_ctx *const *cs, int n, hipStream_t st, BatchArena &ba, LaunchList &L);
+bool batch_dense_ok(const vest_ctx *c);   // every factor pass of c would run the dense contraction
 
 // ---------------------------------------------------------------- workspace
 struct Plan {

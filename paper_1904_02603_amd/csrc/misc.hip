@@ -17,10 +17,10 @@ struct Shape {
 
 // out[j_n][others ascending] = core[j_1..j_N]   (row-major both)
 template <typename T>
-__global__ void __launch_bounds__(256) k_permute(const double *__restrict__ core, Shape sh, int mode, int64_t G,
-                                                 T *__restrict__ out)
+__device__ __forceinline__ void permute_body(const double *__restrict__ core, Shape sh, int mode, int64_t G,
+                                             T *__restrict__ out, int bx)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)bx * blockDim.x + threadIdx.x;
     if (q >= G) return;
     // digits of q in the permuted order: position 0 is mode `mode`, then the
     // other modes ascending
@@ -37,6 +37,65 @@ __global__ void __launch_bounds__(256) k_permute(const double *__restrict__ core
     int64_t flat = 0;
     for (int k = 0; k < sh.N; ++k) flat = flat * sh.J + jv[k];
     out[q] = (T)core[flat];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute(const double *__restrict__ core, Shape sh, int mode, int64_t G,
+                                                 T *__restrict__ out)
+{
+    permute_body<T>(core, sh, mode, G, out, blockIdx.x);
+}
+
+template <typename T>
+struct PermTask {
+    const double *core;
+    T *out;
+    int64_t G;
+    int32_t mode;
+};
+
+// the permuted cores of several contexts of one shape (all modes)
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute_multi(const PermTask<T> *__restrict__ tab,
+                                                       const int32_t *__restrict__ off, int ntask, int total, Shape sh)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const PermTask<T> tk = tab[t];
+        permute_body<T>(tk.core, sh, tk.mode, tk.G, tk.out, b - off[t]);
+    }
+}
+
+template <typename T>
+static bool plan_permute_batch_t(vest_ctx *const *cs, int n, hipStream_t st, BatchArena &ba, LaunchList &L)
+{
+    const int N = cs[0]->N;
+    std::vector<PermTask<T>> tab;
+    std::vector<int32_t> off(1, 0);
+    for (int i = 0; i < n; ++i)
+        for (int m = 0; m < N; ++m) {
+            vest_ctx *c = cs[i];
+            tab.push_back(PermTask<T>{c->core, reinterpret_cast<T *>(c->Gp[m]), c->G, m});
+            off.push_back(off.back() + (int32_t)((c->G + 255) / 256));
+        }
+    const size_t ot = ba.add(tab.data(), sizeof(PermTask<T>) * tab.size());
+    const size_t oo = ba.add(off.data(), 4 * off.size());
+    if (ba.overflow) return false;
+    const PermTask<T> *dt = ba.dptr<PermTask<T>>(ot);
+    const int32_t *doff = ba.dptr<int32_t>(oo);
+    const int ntask = (int)tab.size(), total = off.back();
+    const Shape sh{N, cs[0]->J};
+    L.push_back([=]() {
+        if (total > 0)
+            hipLaunchKernelGGL(k_permute_multi<T>, dim3(total < kBatchGrid ? total : kBatchGrid), dim3(256), 0, st,
+                               dt, doff, ntask, total, sh);
+    });
+    return true;
+}
+
+bool plan_permute_batch(vest_ctx *const *cs, int n, hipStream_t st, BatchArena &ba, LaunchList &L)
+{
+    return cs[0]->f32 ? plan_permute_batch_t<float>(cs, n, st, ba, L) : plan_permute_batch_t<double>(cs, n, st, ba, L);
 }
 
 hipError_t launch_permute_core(vest_ctx *c, int mode)

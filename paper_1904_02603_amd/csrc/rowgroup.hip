@@ -305,10 +305,10 @@ __device__ __forceinline__ void pair_steps(const RowArgs<N, J, T> &a, const Core
 // GA = true : pruned-phase gather contraction from LDS (dynamic LDS of
 //             gather_lds_bytes<N, J, T>() bytes).
 template <int N, int J, typename T, int OP, bool GA>
-__global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *__restrict__ Gp)
+__device__ __forceinline__ void rowgroup_body(const RowArgs<N, J, T> &a, const T *__restrict__ Gp, int bx,
+                                              char *smem)
 {
     constexpr int NA = row_nacc<J, OP>();
-    extern __shared__ __align__(16) char smem[];
     const T *Gt = a.gt;
     const uint32_t *Gnz = a.gnz;
     if constexpr (GA && gather_in_lds(N, J, (int)sizeof(T))) {
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
     }
     const CoreBases<T> Gb = core_bases_if<N, J, T, !GA>(Gp);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int wave = bx * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (wave >= a.nwaves) return;
     const WaveInfo wi = a.waves[wave];
     const int grp = lane >> wi.glog;
@@ -480,20 +480,67 @@ __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *_
     }
 }
 
+template <int N, int J, typename T, int OP, bool GA>
+__global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *__restrict__ Gp)
+{
+    extern __shared__ __align__(16) char smem[];
+    rowgroup_body<N, J, T, OP, GA>(a, Gp, blockIdx.x, smem);
+}
+
+// Several contexts of one shape in one launch (dense contraction): block b of
+// the grid-stride loop is virtual block b - off[t] of task t (a context's
+// RowArgs and permuted core), so one launch carries every job of a serving
+// batch.
+template <int N, int J, typename T>
+struct RowTask {
+    RowArgs<N, J, T> a;
+    const T *Gp;
+    const LongRow *longrows;
+};
+
+template <int N, int J, typename T, int OP>
+__global__ void __launch_bounds__(256) k_rowgroup_multi(const RowTask<N, J, T> *__restrict__ tab,
+                                                        const int32_t *__restrict__ off, int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const RowTask<N, J, T> tk = tab[t];   // arguments in registers, read once
+        rowgroup_body<N, J, T, OP, false>(tk.a, tk.Gp, b - off[t], nullptr);
+    }
+}
+
 // Rows longer than one chunk: sum the chunk partials in a fixed order, then
 // run the same epilogue (one wave per long row).
 template <int N, int J, typename T, int OP>
-__global__ void __launch_bounds__(64) k_rowgroup_long(RowArgs<N, J, T> a, const LongRow *__restrict__ lr)
+__device__ __forceinline__ void rowgroup_long_body(const RowArgs<N, J, T> &a, const LongRow *__restrict__ lr, int bx)
 {
     constexpr int NA = row_nacc<J, OP>();
     __shared__ double sh[NA];
-    const LongRow L = lr[blockIdx.x];
+    const LongRow L = lr[bx];
     sum_partials<NA>(a.partials, L, sh, threadIdx.x);
     if (threadIdx.x == 0) {
         double s[NA];
 #pragma unroll
         for (int v = 0; v < NA; ++v) s[v] = sh[v];
         row_epilogue<N, J, T, OP, double>(a, L.row, s);
+    }
+}
+
+template <int N, int J, typename T, int OP>
+__global__ void __launch_bounds__(64) k_rowgroup_long(RowArgs<N, J, T> a, const LongRow *__restrict__ lr)
+{
+    rowgroup_long_body<N, J, T, OP>(a, lr, blockIdx.x);
+}
+
+template <int N, int J, typename T, int OP>
+__global__ void __launch_bounds__(64) k_rowgroup_long_multi(const RowTask<N, J, T> *__restrict__ tab,
+                                                            const int32_t *__restrict__ off, int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const RowTask<N, J, T> tk = tab[t];
+        rowgroup_long_body<N, J, T, OP>(tk.a, tk.longrows, b - off[t]);
+        __syncthreads();   // the LDS sums are reused by the next long row
     }
 }
 
@@ -538,7 +585,7 @@ __device__ __forceinline__ void swap32(float &lo, float &hi)
 }
 
 template <int J, int MF>
-__global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, const float *__restrict__ Gp)
+__device__ __forceinline__ void rowgroup_mfma_body(const RowArgs<3, J, float> &a, const float *__restrict__ Gp, int bx)
 {
     static_assert(J <= 16, "one K block of 16 (BF16) or J/2 steps of 2 (FP32)");
     constexpr int NA = nacc_vc(J);
@@ -548,7 +595,7 @@ __global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, c
     using AOp = typename std::conditional<MF == MF_BF16, bf16x8, float>::type;
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    const int wave = bx * (blockDim.x / kWave) + (threadIdx.x / kWave);
     if (wave >= a.nwaves) return;  // whole waves only: the matrix ops need every lane
     const WaveInfo wi = a.waves[wave];
     const int grp = lane >> wi.glog;
@@ -680,6 +727,23 @@ __global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, c
     if (has_row && (lane & ((1 << wi.glog) - 1)) == 0) row_epilogue<3, J, float, OP_SWEEP, float>(a, row, s);
 }
 
+template <int J, int MF>
+__global__ void __launch_bounds__(256) k_rowgroup_mfma(RowArgs<3, J, float> a, const float *__restrict__ Gp)
+{
+    rowgroup_mfma_body<J, MF>(a, Gp, blockIdx.x);
+}
+
+template <int J, int MF>
+__global__ void __launch_bounds__(256) k_rowgroup_mfma_multi(const RowTask<3, J, float> *__restrict__ tab,
+                                                             const int32_t *__restrict__ off, int ntask, int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const RowTask<3, J, float> tk = tab[t];
+        rowgroup_mfma_body<J, MF>(tk.a, tk.Gp, b - off[t]);
+    }
+}
+
 // Kernel choice for the contraction of mode `mode` (the factors of the other
 // modes enter).  AUTO compares costs in fused multiply-adds per entry: the
 // dense contraction's sum_{m=2..N} J^m (a quarter of that on the matrix-core
@@ -705,10 +769,9 @@ static bool use_gather(const vest_ctx *c, int mode, bool dense_on_mfma)
 }
 
 template <int N, int J, typename T>
-static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
+static RowArgs<N, J, T> make_row_args(vest_ctx *c, int mode)
 {
     const ModeLayout &L = c->lay[mode];
-    const bool f32 = std::is_same<T, float>::value;
     RowArgs<N, J, T> a{};
     a.waves = L.waves;
     a.nwaves = L.nwaves;
@@ -733,6 +796,14 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
     a.keys = c->key_fac[mode];
     a.rowbuf = c->rowbuf;
     a.ldrb = c->ldrb;
+    return a;
+}
+
+template <int N, int J, typename T>
+static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
+{
+    const ModeLayout &L = c->lay[mode];
+    RowArgs<N, J, T> a = make_row_args<N, J, T>(c, mode);
     const T *Gp = reinterpret_cast<const T *>(c->Gp[mode]);
     const int blocks = (L.nwaves + 3) / 4;
     const bool ga = use_gather(c, mode, (N == 3 && J <= 16 && std::is_same<T, float>::value && op == OP_SWEEP));
@@ -795,6 +866,87 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
 }
 
 bool resid_fuses_slab0(const vest_ctx *c) { return !use_gather(c, c->N - 1, false); }
+
+bool batch_dense_ok(const vest_ctx *c)
+{
+    for (int m = 0; m < c->N; ++m) {
+        const bool mfma = c->N == 3 && c->J <= 16 && c->f32;
+        if (use_gather(c, m, mfma) || use_gather(c, m, false)) return false;
+    }
+    return true;
+}
+
+template <int N, int J, typename T>
+static bool plan_factor_batch_t(vest_ctx *const *cs, int n, int mode, int op, hipStream_t st, BatchArena &ba,
+                                LaunchList &L)
+{
+    if (op != OP_SWEEP && op != OP_RESID_S0) return false;
+    std::vector<RowTask<N, J, T>> tab(n);
+    std::vector<int32_t> off(n + 1, 0), loff(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        vest_ctx *c = cs[i];
+        tab[i].a = make_row_args<N, J, T>(c, mode);
+        tab[i].Gp = reinterpret_cast<const T *>(c->Gp[mode]);
+        tab[i].longrows = c->lay[mode].longrows;
+        off[i + 1] = off[i] + (c->lay[mode].nwaves + 3) / 4;
+        loff[i + 1] = loff[i] + (op == OP_SWEEP ? c->lay[mode].nlong : 0);
+    }
+    const size_t ot = ba.add(tab.data(), sizeof(RowTask<N, J, T>) * n);
+    const size_t oo = ba.add(off.data(), 4 * (n + 1));
+    const size_t ol = ba.add(loff.data(), 4 * (n + 1));
+    if (ba.overflow) return false;
+    const RowTask<N, J, T> *dt = ba.dptr<RowTask<N, J, T>>(ot);
+    const int32_t *doff = ba.dptr<int32_t>(oo), *dloff = ba.dptr<int32_t>(ol);
+    const int total = off[n], ltotal = loff[n];
+    const bool bf16 = cs[0]->d.precision == VEST_BF16;
+    L.push_back([=]() {
+        const int grid = total < kBatchGrid ? total : kBatchGrid;
+        if (total > 0) {
+            bool done = false;
+            if constexpr (N == 3 && J <= 16 && std::is_same<T, float>::value) {
+                if (op == OP_SWEEP) {
+                    const auto *mt = reinterpret_cast<const RowTask<3, J, float> *>(dt);
+                    if (bf16)
+                        hipLaunchKernelGGL((k_rowgroup_mfma_multi<J, MF_BF16>), dim3(grid), dim3(256), 0, st, mt, doff,
+                                           n, total);
+                    else
+                        hipLaunchKernelGGL((k_rowgroup_mfma_multi<J, MF_F32>), dim3(grid), dim3(256), 0, st, mt, doff,
+                                           n, total);
+                    done = true;
+                }
+            }
+            if constexpr (dense_form(N, J)) {
+                if (!done) {
+                    if (op == OP_SWEEP)
+                        hipLaunchKernelGGL((k_rowgroup_multi<N, J, T, OP_SWEEP>), dim3(grid), dim3(256), 0, st, dt,
+                                           doff, n, total);
+                    else
+                        hipLaunchKernelGGL((k_rowgroup_multi<N, J, T, OP_RESID_S0>), dim3(grid), dim3(256), 0, st, dt,
+                                           doff, n, total);
+                }
+            }
+        }
+        if (ltotal > 0) {
+            const int lg = ltotal < kBatchGrid ? ltotal : kBatchGrid;
+            hipLaunchKernelGGL((k_rowgroup_long_multi<N, J, T, OP_SWEEP>), dim3(lg), dim3(64), 0, st, dt, dloff, n,
+                               ltotal);
+        }
+    });
+    return true;
+}
+
+bool plan_factor_batch(vest_ctx *const *cs, int n, int mode, int op, hipStream_t st, BatchArena &ba, LaunchList &L)
+{
+    const vest_ctx *c = cs[0];
+    if (!dense_form(c->N, c->J)) return false;
+#define VEST_CASE(NN, JJ)                                                                        \
+    if (c->N == NN && c->J == JJ)                                                                \
+        return c->f32 ? plan_factor_batch_t<NN, JJ, float>(cs, n, mode, op, st, ba, L)           \
+                      : plan_factor_batch_t<NN, JJ, double>(cs, n, mode, op, st, ba, L);
+    VEST_SHAPES(VEST_CASE)
+#undef VEST_CASE
+    return false;
+}
 
 hipError_t launch_rowgroup(vest_ctx *c, int mode, int op)
 {

@@ -1,8 +1,14 @@
 // Request loop of libvest (include/vest_serve.h): admission by device
-// footprint into one arena, one stream per job slot, one iteration of Alg. 2
-// in flight per admitted job.
+// footprint into one arena, one stream per job slot; admitted jobs of one
+// class (order, rank, precision, entry count within a factor of 4) advance
+// together, one batched
+// iteration of Alg. 2 at a time (vest_iterate_many: every kernel of the
+// iteration launched once for the whole class), classes on streams of their
+// own; a job that does not fit the batched path runs alone on its slot's
+// stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -99,8 +105,10 @@ struct Job {
     Block blk[7];
     vest_ctx *ctx = nullptr;
     int slot = -1;
+    int klass = -1;          // shape class (batched iterations), -1 until admitted
     int32_t iters_done = 0;
-    bool inflight = false;
+    bool inflight = false;   // an iteration is enqueued and not yet complete
+    bool in_batch = false;   // ... as part of its class's batch (else on its slot stream)
     // results (host)
     std::vector<double> res_fac, res_core;
     double loss[5] = {0, 0, 0, 0, 0};
@@ -140,9 +148,28 @@ struct Job {
 
 }  // namespace
 
+// Jobs of one shape advance in batched iterations on the class's stream; the
+// task tables of a batch are staged in pinned host memory and mirrored in a
+// device buffer (both allocated when the class first appears).
+struct Klass {
+    int N = 0, J = 0, precision = 0, bucket = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    char *dev = nullptr;         // device table buffer
+    char *host = nullptr;        // pinned staging of the tables
+    bool usable = false;         // buffers in place
+    bool inflight = false;
+    std::vector<int64_t> batch;  // jobs of the batch in flight
+};
+
+constexpr size_t kClassTable = 1u << 20;
+
 struct vest_server {
     char *base = nullptr;
     Arena arena;
+    std::vector<Klass> classes;
+    double *pinned_loss = nullptr;   // the host buffer vest_loss of a retiring job reads into
+    int64_t batches = 0, batched_job_iters = 0;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<int64_t> slot_job;   // job id per slot, -1 if free
@@ -249,6 +276,41 @@ bool admit(vest_server *s, Job &j, int slot)
     return true;
 }
 
+// Jobs of a class advance in lockstep, so a class also bounds the spread of
+// its jobs' sizes: entries within a factor of 4 (a small job is not held back
+// by a large one's iterations).
+int size_bucket(int64_t nnz)
+{
+    int b = 0;
+    while (nnz >= 4) {
+        nnz >>= 2;
+        ++b;
+    }
+    return b;
+}
+
+int klass_of(vest_server *s, const Job &j)
+{
+    const int N = j.N, J = j.in.desc.ranks[0], pr = j.in.desc.precision, sb = size_bucket(j.in.desc.nnz);
+    for (size_t k = 0; k < s->classes.size(); ++k) {
+        const Klass &K = s->classes[k];
+        if (K.N == N && K.J == J && K.precision == pr && K.bucket == sb) return (int)k;
+    }
+    Klass K;
+    K.N = N;
+    K.J = J;
+    K.precision = pr;
+    K.bucket = sb;
+    hipError_t e = hipStreamCreateWithFlags(&K.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&K.event, hipEventDisableTiming);
+    // the tables live outside the arena, which is the jobs' budget
+    if (e == hipSuccess && hipMalloc((void **)&K.dev, kClassTable) == hipSuccess &&
+        hipHostMalloc((void **)&K.host, kClassTable, hipHostMallocDefault) == hipSuccess)
+        K.usable = true;
+    s->classes.push_back(K);
+    return (int)s->classes.size() - 1;
+}
+
 int enqueue_iteration(vest_server *s, Job &j)
 {
     int rc = VEST_OK;
@@ -258,13 +320,61 @@ int enqueue_iteration(vest_server *s, Job &j)
     hipError_t e = hipEventRecord(s->events[j.slot], s->streams[j.slot]);
     if (e != hipSuccess) return hip_fail(e, "event record");
     j.inflight = true;
+    j.in_batch = false;
     return VEST_OK;
+}
+
+// One batched iteration of every idle job of class k that has iterations
+// left; jobs the batched path does not take run alone.  Returns the jobs
+// that failed (to be retired by the caller).
+std::vector<int64_t> enqueue_class(vest_server *s, int k)
+{
+    Klass &K = s->classes[k];
+    std::vector<int64_t> failed, ids;
+    std::vector<vest_ctx *> cs;
+    for (int64_t id : s->active) {
+        Job &j = *s->jobs[id];
+        if (j.klass == k && !j.inflight && j.iters_done < j.in.iterations) {
+            ids.push_back(id);
+            cs.push_back(j.ctx);
+        }
+    }
+    if (ids.empty() || K.inflight) return failed;
+    int rc = VEST_EUNSUPPORTED;
+    if (K.usable)
+        rc = vest_iterate_many(cs.data(), (int32_t)cs.size(), K.stream, K.dev, K.host, kClassTable);
+    if (rc == VEST_OK) {
+        hipError_t e = hipEventRecord(K.event, K.stream);
+        if (e == hipSuccess) {
+            K.inflight = true;
+            K.batch = ids;
+            for (int64_t id : ids) {
+                Job &j = *s->jobs[id];
+                j.inflight = true;
+                j.in_batch = true;
+            }
+            s->batches++;
+            s->batched_job_iters += (int64_t)ids.size();
+            return failed;
+        }
+        rc = hip_fail(e, "event record");
+        for (int64_t id : ids) failed.push_back(id);
+        return failed;
+    }
+    // not batched: each job alone on its slot's stream
+    for (int64_t id : ids) {
+        Job &j = *s->jobs[id];
+        if (enqueue_iteration(s, j) != VEST_OK) failed.push_back(id);
+    }
+    return failed;
 }
 
 // Loss, result copies, release.  Synchronises the job's stream.
 void retire(vest_server *s, Job &j)
 {
     hipStream_t st = s->streams[j.slot];
+    j.ctx->host_red = s->pinned_loss;   // server-owned; not freed by vest_destroy
+    j.ctx->host_red_owned = false;
     int rc = vest_loss(j.ctx, j.loss);
     if (rc == VEST_OK) {
         JobPtrs p = job_ptrs(s, j);
@@ -306,6 +416,7 @@ int vest_server_create(size_t device_bytes, int32_t slots, vest_server **out)
         return hip_fail(e, "server arena");
     }
     s->arena.reset(device_bytes / kAlign * kAlign);
+    if (hipHostMalloc((void **)&s->pinned_loss, 64, hipHostMallocDefault) != hipSuccess) s->pinned_loss = nullptr;
     s->streams.assign(slots, nullptr);
     s->events.assign(slots, nullptr);
     s->slot_job.assign(slots, -1);
@@ -353,11 +464,26 @@ int vest_server_progress(vest_server *s, int32_t *completed)
 {
     if (!s) { set_error("null server"); return VEST_EINVAL; }
     int32_t done = 0;
-    // 1. advance admitted jobs
+    // 1. batches that completed
+    for (Klass &K : s->classes) {
+        if (!K.inflight) continue;
+        hipError_t q = hipEventQuery(K.event);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return hip_fail(q, "event query");
+        for (int64_t id : K.batch) {
+            Job &j = *s->jobs[id];
+            j.inflight = false;
+            j.in_batch = false;
+            ++j.iters_done;
+        }
+        K.inflight = false;
+        K.batch.clear();
+    }
+    // 2. single iterations that completed; retire finished jobs
     std::vector<int64_t> still;
     for (int64_t id : s->active) {
         Job &j = *s->jobs[id];
-        if (j.inflight) {
+        if (j.inflight && !j.in_batch) {
             hipError_t q = hipEventQuery(s->events[j.slot]);
             if (q == hipErrorNotReady) {
                 still.push_back(id);
@@ -367,23 +493,19 @@ int vest_server_progress(vest_server *s, int32_t *completed)
             j.inflight = false;
             ++j.iters_done;
         }
-        if (j.iters_done < j.in.iterations) {
-            int rc = enqueue_iteration(s, j);
-            if (rc != VEST_OK) {
-                retire(s, j);
-                j.state = VEST_JOB_FAILED;
-                j.error = rc;
-                ++done;
-                continue;
-            }
+        if (j.inflight) {   // its class's batch is still running
             still.push_back(id);
-        } else {
+            continue;
+        }
+        if (j.iters_done >= j.in.iterations) {
             retire(s, j);
             ++done;
+            continue;
         }
+        still.push_back(id);
     }
     s->active.swap(still);
-    // 2. admit queued jobs in arrival order; later jobs fill in when the head
+    // 3. admit queued jobs in arrival order; later jobs fill in when the head
     //    does not fit yet
     for (auto it = s->queue.begin(); it != s->queue.end();) {
         int slot = -1;
@@ -400,19 +522,28 @@ int vest_server_progress(vest_server *s, int32_t *completed)
             continue;
         }
         if (j.state == VEST_JOB_ACTIVE) {
-            int rc = enqueue_iteration(s, j);
-            if (rc != VEST_OK) {
-                retire(s, j);
-                j.state = VEST_JOB_FAILED;
-                j.error = rc;
-                ++done;
-            } else {
-                s->active.push_back(j.id);
-            }
+            j.klass = klass_of(s, j);
+            s->active.push_back(j.id);
         } else {
             ++done;  // failed at admission
         }
         it = s->queue.erase(it);
+    }
+    // 4. the next iteration of every idle job, batched per class
+    for (size_t k = 0; k < s->classes.size(); ++k) {
+        std::vector<int64_t> failed = enqueue_class(s, (int)k);
+        if (failed.empty()) continue;
+        (void)hipStreamSynchronize(s->classes[k].stream);
+        for (int64_t id : failed) {
+            Job &j = *s->jobs[id];
+            const int32_t err = j.ctx && j.ctx->dead ? VEST_EDEVICE : VEST_EUNSUPPORTED;
+            j.inflight = false;
+            retire(s, j);
+            j.state = VEST_JOB_FAILED;
+            j.error = err;
+            ++done;
+            s->active.erase(std::find(s->active.begin(), s->active.end(), id));
+        }
     }
     if (completed) *completed = done;
     return VEST_OK;
@@ -469,6 +600,8 @@ int vest_server_stats(vest_server *s, int64_t *out)
     out[3] = (int64_t)s->arena.used();
     out[4] = (int64_t)s->arena.size();
     out[5] = (int64_t)s->arena.largest();
+    out[6] = s->batches;
+    out[7] = s->batched_job_iters;
     return VEST_OK;
 }
 
@@ -477,11 +610,23 @@ int vest_server_destroy(vest_server *s)
     if (!s) return VEST_OK;
     for (hipStream_t st : s->streams)
         if (st) hipStreamSynchronize(st);
+    for (Klass &K : s->classes)
+        if (K.stream) hipStreamSynchronize(K.stream);
     for (int64_t id : s->active) {
         Job &j = *s->jobs[id];
         if (j.ctx) vest_destroy(j.ctx);
         j.ctx = nullptr;
     }
+    for (Klass &K : s->classes) {
+        if (K.stream) {
+            hipStreamSynchronize(K.stream);
+            hipStreamDestroy(K.stream);
+        }
+        if (K.event) hipEventDestroy(K.event);
+        if (K.host) hipHostFree(K.host);
+        if (K.dev) hipFree(K.dev);
+    }
+    if (s->pinned_loss) hipHostFree(s->pinned_loss);
     for (hipEvent_t ev : s->events)
         if (ev) hipEventDestroy(ev);
     for (hipStream_t st : s->streams)

@@ -24,7 +24,7 @@ EXPORTS = ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep
            "vest_responsibility", "vest_prune", "vest_loss", "vest_normalize", "vest_count_nonzeros",
            "vest_export", "vest_test_error", "vest_value_keys", "vest_compact", "vest_set_kernel",
            "vest_layout_stats", "vest_slab_timing", "vest_slab_time", "vest_destroy", "vest_strerror",
-           "vest_last_error", "vest_model_error_noalloc",
+           "vest_last_error", "vest_model_error_noalloc", "vest_iterate_many",
            "vest_server_create", "vest_server_submit", "vest_server_progress", "vest_server_status",
            "vest_server_fetch", "vest_server_stats", "vest_server_destroy"]
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -76,6 +76,7 @@ def load_library(path=LIB_PATH):
     lib.vest_export.argtypes = [vp, vp, vp, vp, vp]
     lib.vest_test_error.argtypes = [vp, vp, vp, i64, vp]
     lib.vest_model_error_noalloc.argtypes = [PD, vp, vp, vp, vp, vp, i64, vp]
+    lib.vest_iterate_many.argtypes = [vp, i32, vp, vp, vp, C.c_size_t]
     lib.vest_value_keys.argtypes = [vp, vp, vp]
     lib.vest_layout_stats.argtypes = [vp, i32, vp]
     lib.vest_slab_timing.argtypes = [vp, i32]
@@ -98,7 +99,7 @@ def load_library(path=LIB_PATH):
     for name in ["vest_workspace_bytes", "vest_init", "vest_sweep_factor", "vest_sweep_core",
                  "vest_responsibility", "vest_prune", "vest_loss", "vest_normalize", "vest_count_nonzeros",
                  "vest_export", "vest_test_error", "vest_value_keys", "vest_compact", "vest_set_kernel",
-                 "vest_layout_stats", "vest_destroy", "vest_model_error_noalloc"]:
+                 "vest_layout_stats", "vest_destroy", "vest_model_error_noalloc", "vest_iterate_many"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -307,6 +308,33 @@ class VestContext:
             pass
 
 
+class Batch:
+    """vest_iterate_many: one Alg. 2 iteration of several contexts of one
+    shape in one sequence of launches.  Owns a device table buffer and a
+    pinned host staging buffer of `table_bytes`."""
+
+    def __init__(self, table_bytes=4 << 20, device="cuda"):
+        self.lib = load_library()
+        self.bytes = int(table_bytes)
+        self.dev = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+        self.host = torch.empty(self.bytes, dtype=torch.uint8, pin_memory=True)
+
+    def iterate(self, ctxs, stream=None, wait=True):
+        """Returns VEST_OK, or EUNSUPPORTED when the batched path does not
+        take these contexts (nothing was enqueued then).  The staging buffer
+        is reused, so by default the stream is drained first (wait=False when
+        the previous upload from this Batch is known to be complete)."""
+        st = stream if stream is not None else torch.cuda.current_stream()
+        arr = (C.c_void_p * len(ctxs))(*[c.ctx.value for c in ctxs])
+        if wait:
+            st.synchronize()
+        rc = self.lib.vest_iterate_many(arr, len(ctxs), C.c_void_p(st.cuda_stream), _ptr(self.dev), _ptr(self.host),
+                                        C.c_size_t(self.bytes))
+        if rc not in (OK, EUNSUPPORTED):
+            _check(rc, "vest_iterate_many")
+        return rc
+
+
 NOALLOC_MAX_ENTRIES = 1 << 24
 
 
@@ -398,9 +426,10 @@ class VestServer:
         return fac, core, dict(zip(["sse", "xnorm2", "reg", "loss", "re"], list(loss)))
 
     def stats(self):
-        out = (C.c_int64 * 6)()
+        out = (C.c_int64 * 8)()
         _check(self.lib.vest_server_stats(self.srv, out), "vest_server_stats")
-        return dict(zip(["queued", "active", "finished", "bytes_used", "bytes_total", "largest_free"], list(out)))
+        return dict(zip(["queued", "active", "finished", "bytes_used", "bytes_total", "largest_free", "batches",
+                         "batched_job_iterations"], list(out)))
 
     def close(self):
         if self.srv is not None and self.srv.value:

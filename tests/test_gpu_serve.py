@@ -2,10 +2,14 @@
 
 Jobs of different order, rank, regulariser and precision run through one
 server with fewer slots than jobs, so some wait and the admitted ones overlap
-on the device; each result must equal bit for bit the same job run alone
-through the plain context (every kernel sums in a fixed order, so the mix
-cannot change a result).  The arena bound, the rejection of a job larger than
-the arena and the failure of a job with invalid data are checked as well.
+on the device, jobs of one shape in batched iterations (vest_iterate_many);
+each result must equal bit for bit the same job run alone through the plain
+context (every kernel sums in a fixed order and the batched kernels run the
+same per-job arithmetic, so the mix cannot change a result).  Served results
+are checked against the oracle (FP64 at the FP64 bar, FP32 / split-BF16
+within 1e-4 relative RE and factor RMSE).  The arena bound, the rejection of
+a job larger than the arena and the failure of a job with invalid data are
+checked as well.
 """
 import time
 
@@ -69,8 +73,11 @@ def test_results_in_the_mix_equal_results_alone():
     ids = [srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec,
                       iterations=iters) for p, reg, lam, prec in ins]
     peak = drain(srv, ids)
-    say("peak active", peak["active"])
+    st = srv.stats()
+    say("peak active", peak["active"], "batches", st["batches"], "batched job-iterations",
+        st["batched_job_iterations"])
     assert peak["active"] >= 2  # jobs overlapped
+    assert st["batched_job_iterations"] == iters * len(JOBS)   # every iteration ran batched
     for k, (jid, (p, reg, lam, prec)) in enumerate(zip(ids, ins)):
         st = srv.status(jid)
         assert st["state"] == v.JOB_DONE, (k, st)
@@ -124,4 +131,33 @@ def test_oversized_and_invalid_jobs():
     assert ei.value.code == v.ESTATE
     srv.fetch(jg)
     assert srv.stats()["bytes_used"] == 0
+    srv.close()
+
+
+def test_served_jobs_match_oracle():
+    from oracle.oracle import Oracle
+    from test_gpu_parity import rel_err, rms_err
+    v = V()
+    iters = 3
+    picks = [0, 1, 2, 3, 0]   # FP32, BF16, FP32 order 4, FP64 Zipf; a second FP32 job of the first shape
+    ins = [job_inputs(k) for k in picks]
+    srv = v.VestServer(1 << 30, 8)
+    ids = [srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec,
+                      iterations=iters) for p, reg, lam, prec in ins]
+    drain(srv, ids)
+    for jid, (p, reg, lam, prec) in zip(ids, ins):
+        fac, core, loss = srv.fetch(jid)
+        o = Oracle(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam)
+        for _ in range(iters):
+            o.iteration()
+        ol = o.loss()
+        gap = abs(loss["re"] - ol["re"]) / ol["re"]
+        fr = max(rms_err(f, of) for f, of in zip(fac, o.factors))
+        say(prec, "served: RE gap %.2e, factor rel RMSE %.2e" % (gap, fr))
+        if prec == v.FP64:
+            for f, of in zip(fac, o.factors):
+                assert rel_err(f, of) <= 1e-10
+            assert rel_err(core, o.core) <= 1e-10
+        else:
+            assert gap <= 1e-4 and fr <= 1e-4
     srv.close()
