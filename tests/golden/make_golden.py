@@ -24,7 +24,9 @@ package's synth module):
                 each.
   config4-auto  the order-4 Zipf workload 50k x 50k x 1000 x 24, ranks 8^4,
                 L_F 0.01, at 10^6 entries: VeST^auto (elbow rule, sparsity cap
-                0.95), up to 20 iterations, then the column normalisation.
+                0.95), up to 20 iterations, then the column normalisation;
+                also the whole state (factors, core, marking tables) the
+                last iteration starts from.
 """
 import hashlib
 import json
@@ -141,6 +143,14 @@ def config4_auto(p, out, iters=20, cap=0.95):
     re_hist, steps = [], []
     t0 = time.time()
     for t in range(1, iters + 1):
+        if t == iters:
+            # the state the last iteration starts from: a GPU context loaded
+            # with it runs that iteration from identical inputs
+            for n in range(len(dims)):
+                out["pre_factor_m%d" % n] = o.factors[n].copy()
+                out["pre_fmask_m%d" % n] = np.packbits(o.fmask[n].astype(bool).ravel())
+            out["pre_core"] = o.core.copy()
+            out["pre_cmask"] = o.cmask.astype(np.uint8).copy()
         o.iteration()
         L = loss_vec(o)
         re_hist.append(L[4])
