@@ -153,6 +153,9 @@ int vest_prune(vest_ctx *ctx, int64_t core_k, const int64_t *factor_k);
  *   out[0] SSE = sum_Omega (X - B)^2    out[1] ||X||^2 over Omega
  *   out[2] regulariser term             out[3] loss = out[0] + out[2]
  *   out[4] RE = sqrt(out[0] / out[1])
+ * Right after vest_sweep_core, out[0] is formed from the last core slab's
+ * statistics (sum e^2 - 2 D.rr + D^T H D with D that slab's change; equal to
+ * the direct sum up to rounding order) instead of a pass over the residual.
  * out is a host array of 5 doubles.  Synchronises the stream. */
 int vest_loss(vest_ctx *ctx, double *out);
 

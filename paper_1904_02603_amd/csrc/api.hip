@@ -154,9 +154,10 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     const int gw = gram_width(J);
     const int64_t Il = c->d.dims[N - 1];
     c->ldrb = rowbuf_width(N, J, (int)ts);
-    const int64_t gsq = (int64_t)gw * gw > (int64_t)keys_width(N, J, (int)ts) * round8(2 * J)
-                            ? (int64_t)gw * gw
-                            : (int64_t)keys_width(N, J, (int)ts) * round8(2 * J);
+    int64_t gsq = (int64_t)gw * gw > (int64_t)keys_width(N, J, (int)ts) * round8(2 * J)
+                      ? (int64_t)gw * gw
+                      : (int64_t)keys_width(N, J, (int)ts) * round8(2 * J);
+    if (gsq < gram_core_cells(J)) gsq = gram_core_cells(J);
     // (keys_width x round8(2J) also bounds the R-only batches: round8(J S) x round8(J))
     c->rowbuf = (double *)take(Il * c->ldrb * 8);
     c->kp = (double *)take(Il * gw * 8);
@@ -166,6 +167,7 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     int na = nacc_vc(J) > 2 * J ? nacc_vc(J) : 2 * J;
     na = na > keys_nacc(N, J, (int)ts) ? na : keys_nacc(N, J, (int)ts);
     c->partials = (double *)take(p.chunk_bound * na * 8);
+    c->wsum = (double *)take(p.wave_bound[N - 1] * 8);
     c->partials_side = (double *)take(p.chunk_bound * na * 8);
     if (!gather_in_lds(N, J, (int)ts)) {
         c->gt = take((size_t)c->G * ts);
@@ -182,6 +184,7 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
         c->pkey_core = (double *)take(c->G * 8);
     }
     c->red = (double *)take((16 * kLossBlocks + 64) * 8);
+    c->sse_lag = c->red + 16 * kLossBlocks + 32;
     c->flags = (int32_t *)take(64);
     c->sel_hist = (uint32_t *)take((size_t)(VEST_MAX_ORDER + 1) * 4096 * 4);
     c->sel_state = (char *)take((size_t)(VEST_MAX_ORDER + 1) * 24);
@@ -249,7 +252,13 @@ static int ensure_ag(vest_ctx *c)
 
 static int ensure_residual(vest_ctx *c)
 {
-    if (c->e_valid && c->ms_valid) return VEST_OK;
+    if (c->e_valid && c->ms_valid) {
+        if (c->e_lag) {
+            CALL_HIP(c, launch_lag_apply(c), "residual catch-up");
+            c->e_lag = false;
+        }
+        return VEST_OK;
+    }
     int rc = ensure_ag(c);
     if (rc) return rc;
     rc = ensure_gp(c, c->N - 1);
@@ -257,6 +266,7 @@ static int ensure_residual(vest_ctx *c)
     CALL_HIP(c, launch_rowgroup(c, c->N - 1, OP_RESID), "residual");
     c->e_valid = true;
     c->ms_valid = true;
+    c->e_lag = false;
     return VEST_OK;
 }
 
@@ -423,8 +433,11 @@ int vest_sweep_core(vest_ctx *c)
         CALL_HIP(c, launch_rowgroup(c, c->N - 1, fused ? OP_RESID_S0 : OP_RESID), "residual");
         c->e_valid = true;
         c->ms_valid = true;
+        c->e_lag = false;
+    } else if ((rc = ensure_residual(c))) {   // a residual lagging the previous core sweep catches up
+        return rc;
     }
-    CALL_HIP(c, launch_core_sweep(c, fused), "core sweep");
+    CALL_HIP(c, launch_core_sweep(c, fused), "core sweep");   // sets e_lag
     if (c->padded) CALL_HIP(c, launch_pad_out_core(c), "padded copy-out");
     c->core_version++;
     c->e_valid = true;
@@ -482,6 +495,7 @@ int vest_iterate_many(vest_ctx *const *cs, int32_t n, void *stream, void *dev_ta
         for (int m = 0; m < c->N; ++m) c->gp_version[m] = c->core_version;
         c->e_valid = true;
         c->ms_valid = true;
+        c->e_lag = ipow(c->J, c->N - 2) > 1;   // as in the single-context core sweep
         c->hdiag_valid = true;
     }
     return VEST_OK;
@@ -573,9 +587,11 @@ int vest_loss(vest_ctx *c, double *out)
     int rc = live(c);
     if (rc) return rc;
     if (!out) { set_error("null output"); return VEST_EINVAL; }
-    if ((rc = ensure_residual(c))) return rc;
+    // after a core sweep the SSE is already formed (the residual lags)
+    const bool lagged = c->e_valid && c->ms_valid && c->e_lag;
+    if (!lagged && (rc = ensure_residual(c))) return rc;
     double *dout = c->red + 16 * kLossBlocks;
-    CALL_HIP(c, launch_loss(c, dout), "loss");
+    CALL_HIP(c, launch_loss(c, dout, lagged ? c->sse_lag : nullptr), "loss");
     // the two sums come back through pinned host memory (a direct copy, no
     // pageable staging), allocated on the first call, freed by vest_destroy
     if (!c->host_red) CALL_HIP(c, hipHostMalloc((void **)&c->host_red, 64, hipHostMallocDefault), "pinned buffer");

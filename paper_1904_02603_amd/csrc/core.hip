@@ -49,6 +49,7 @@ struct SlabArgs {
     double *rowbuf;               // [I_{N-1}][ldrb]
     int32_t ldrb;
     double *partials;
+    double *wsum;                 // per wave: sum of e^2 after the correction (k_slab with E2)
     int32_t blead[kKeyAccMax / 2 * NL];  // k_slabkeys: leading indices of each slab of the batch
 };
 
@@ -63,7 +64,9 @@ struct SlabArgs {
 template <typename T>
 __host__ __device__ constexpr int slab_u() { return sizeof(T) == 4 ? 4 : 2; }
 
-template <int N, int J, typename T, bool ACC>
+// With E2 every wave also writes the sum of e^2 over its entries, e taken
+// after the previous slab's change (the residual this slab's statistics see).
+template <int N, int J, typename T, bool ACC, bool E2 = false>
 __device__ __forceinline__ void slab_body(const SlabArgs<N, J, T> &a, int bx)
 {
     constexpr int NA = nacc_vc(J);
@@ -95,6 +98,7 @@ __device__ __forceinline__ void slab_body(const SlabArgs<N, J, T> &a, int bx)
     T s[NA];
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = T(0);
+    double e2 = 0.0;
 
     // the leading indices of the next batch are loaded one batch ahead, so the
     // column gathers they address need not wait for them
@@ -148,6 +152,7 @@ __device__ __forceinline__ void slab_body(const SlabArgs<N, J, T> &a, int bx)
                 e -= pp[q] * du;
                 if (ok[q]) st_stream(e, a.e + sl[q]);
             }
+            if constexpr (E2) e2 += (double)e * (double)e;   // zero for padding slots
             if constexpr (ACC) {
                 T w[J];
 #pragma unroll
@@ -165,6 +170,11 @@ __device__ __forceinline__ void slab_body(const SlabArgs<N, J, T> &a, int bx)
 #pragma unroll
             for (int m = 0; m < NI; ++m) ii[q][m] = ni[q][m];
     }
+    if constexpr (E2) {
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m >>= 1) e2 += __shfl_xor(e2, m);
+        if (lane == 0) a.wsum[wave] = e2;
+    }
     if constexpr (ACC) {
         group_reduce<NA, T>(s, wi.glog);
         if (wi.chunk >= 0) {
@@ -179,22 +189,22 @@ __device__ __forceinline__ void slab_body(const SlabArgs<N, J, T> &a, int bx)
     }
 }
 
-template <int N, int J, typename T, bool ACC>
+template <int N, int J, typename T, bool ACC, bool E2 = false>
 __global__ void __launch_bounds__(256) k_slab(SlabArgs<N, J, T> a)
 {
-    slab_body<N, J, T, ACC>(a, blockIdx.x);
+    slab_body<N, J, T, ACC, E2>(a, blockIdx.x);
 }
 
 // Several contexts of one shape in one launch (virtual block b - off[t] of
 // task t; see k_rowgroup_multi).
-template <int N, int J, typename T, bool ACC>
+template <int N, int J, typename T, bool ACC, bool E2 = false>
 __global__ void __launch_bounds__(256) k_slab_multi(const SlabArgs<N, J, T> *__restrict__ tab,
                                                     const int32_t *__restrict__ off, int ntask, int total)
 {
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int t = task_of(off, ntask, b);
         const SlabArgs<N, J, T> a = tab[t];   // arguments in registers, read once
-        slab_body<N, J, T, ACC>(a, b - off[t]);
+        slab_body<N, J, T, ACC, E2>(a, b - off[t]);
     }
 }
 
@@ -516,19 +526,6 @@ struct GramTask {
     int32_t ldrb, ldkp, rows;
 };
 
-template <int W1, int W2>
-__global__ void __launch_bounds__(64 * ((W1 + 15) / 16)) k_gram_multi(const GramTask *__restrict__ tab,
-                                                                       const int32_t *__restrict__ off, int ntask,
-                                                                       int total)
-{
-    for (int b = blockIdx.x; b < total; b += gridDim.x) {
-        const int t = task_of(off, ntask, b);
-        const GramTask tk = tab[t];
-        gram_body<W1, W2>(tk.rb, tk.ldrb, tk.kp, tk.ldkp, tk.nrows, tk.rows, tk.part, b - off[t]);
-        __syncthreads();   // the staged rows in LDS are reused by the next partial
-    }
-}
-
 template <int W1>
 constexpr int gram_threads() { return 64 * ((W1 + 15) / 16); }
 
@@ -545,11 +542,177 @@ static int gram_rows(int64_t nrows)
     return rows;
 }
 
+// Partial Gram product of one slab in the core sweep, over `rows` rows of the
+// last mode, on the FP64 matrix cores.  Of rb_r^T kp_r (rb_r = [R_r | M_r],
+// kp_r = [a_r | (a a^T)_r]) the solve reads two blocks: M^T (a a^T), the slab's
+// Gram matrix in symmetric-pair form (nm x nm, nm = J (J + 1) / 2), and R^T a,
+// its right-hand side (J x J); the two cross blocks are not formed.  Wave ti
+// owns the 16-row band ti of the M block and its TM tiles.  The R x a tile is
+// shared: wave w takes the k-steps w, w + TM, ... of every 32-row sub-block
+// and the TM accumulators are added in wave order at the end.  The next
+// sub-block's operands are loaded before the current one's products are
+// issued.  Partial layout: the M block (16 TM x 16 TM, row-major, padding
+// rows and columns zero), then the 16 x 16 R x a tile.
+template <int J>
+__device__ __forceinline__ void gram_core_body(const double *__restrict__ rb, int ldrb, const double *__restrict__ kp,
+                                               int ldkp, int64_t nrows, int rows, double *__restrict__ part, int bx)
+{
+    constexpr int NM = gram_nm(J), TM = gram_tm(J), MW = 16 * TM;
+    constexpr int SUB = 32, KS = SUB / 4;   // rows per sub-block, k-steps per sub-block
+    constexpr int KW = J + NM;              // staged kp columns: a, then a a^T
+    constexpr int NT = 64 * TM;
+    constexpr int PER = (SUB * KW + NT - 1) / NT;
+    constexpr int KR = (KS + TM - 1) / TM;  // R x a k-steps of one wave per sub-block
+    static_assert(kGramRows % SUB == 0, "sub-blocks of 32 rows");
+    __shared__ double skp[SUB * KW];
+    __shared__ double sred[TM][4][kWave];
+    const int lane = threadIdx.x & (kWave - 1), ti = threadIdx.x / kWave;
+    const int64_t r0 = (int64_t)bx * rows;
+    const int cm = 16 * ti + (lane & 15);   // this lane's M column (A operand)
+    const int cr = lane & 15;               // this lane's R column
+    // B operand columns of the staged rows: tile tj reads a a^T pair 16 tj + (lane & 15)
+    int bcol[TM];
+    bool bok[TM];
+#pragma unroll
+    for (int tj = 0; tj < TM; ++tj) {
+        bok[tj] = 16 * tj + (lane & 15) < NM;
+        bcol[tj] = bok[tj] ? J + 16 * tj + (lane & 15) : 0;
+    }
+    const bool rok = cr < J;
+    f64x4 acc[TM], racc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int tj = 0; tj < TM; ++tj) acc[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double v[PER], am[KS], ar[KR];
+    auto load = [&](int s0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = threadIdx.x + i * NT;
+            const int rr = q / KW, cc = q % KW;
+            const int64_t r = r0 + s0 + rr;
+            v[i] = (q < SUB * KW && s0 + rr < rows && r < nrows) ? kp[r * ldkp + cc] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int rr = 4 * k + (lane >> 4);
+            const int64_t r = r0 + s0 + rr;
+            am[k] = (s0 + rr < rows && r < nrows && cm < NM) ? rb[r * ldrb + J + cm] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+            const int k = ti + kk * TM;
+            const int rr = 4 * k + (lane >> 4);
+            const int64_t r = r0 + s0 + rr;
+            ar[kk] = (k < KS && s0 + rr < rows && r < nrows && rok) ? rb[r * ldrb + cr] : 0.0;
+        }
+    };
+    load(0);
+    for (int s0 = 0; s0 < rows; s0 += SUB) {
+        __syncthreads();   // the previous sub-block's reads of skp are done
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int q = threadIdx.x + i * NT;
+            if (q < SUB * KW) skp[q] = v[i];
+        }
+        __syncthreads();
+        double cam[KS], car[KR];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) cam[k] = am[k];
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) car[kk] = ar[kk];
+        if (s0 + SUB < rows) load(s0 + SUB);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int rr = 4 * k + (lane >> 4);
+#pragma unroll
+            for (int tj = 0; tj < TM; ++tj) {
+                const double b = bok[tj] ? skp[rr * KW + bcol[tj]] : 0.0;
+                acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(cam[k], b, acc[tj], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+            const int k = ti + kk * TM;
+            if (k < KS) {
+                const int rr = 4 * k + (lane >> 4);
+                const double b = rok ? skp[rr * KW + cr] : 0.0;
+                racc = __builtin_amdgcn_mfma_f64_16x16x4f64(car[kk], b, racc, 0, 0, 0);
+            }
+        }
+    }
+    double *o = part + (int64_t)bx * gram_core_cells(J);
+#pragma unroll
+    for (int tj = 0; tj < TM; ++tj) {
+        const int j = 16 * tj + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 16 * ti + 4 * q + (lane >> 4);
+            o[i * MW + j] = acc[tj][q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sred[ti][q][lane] = racc[q];
+    __syncthreads();
+    if (ti == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double t = sred[0][q][lane];
+            for (int w = 1; w < TM; ++w) t += sred[w][q][lane];
+            o[MW * MW + (4 * q + (lane >> 4)) * 16 + (lane & 15)] = t;
+        }
+    }
+}
+
+template <int J>
+__global__ void __launch_bounds__(64 * gram_tm(J)) k_gram_core(const double *__restrict__ rb, int ldrb,
+                                                                const double *__restrict__ kp, int ldkp,
+                                                                int64_t nrows, int rows, double *__restrict__ part)
+{
+    gram_core_body<J>(rb, ldrb, kp, ldkp, nrows, rows, part, blockIdx.x);
+}
+
+template <int J>
+__global__ void __launch_bounds__(64 * gram_tm(J)) k_gram_core_multi(const GramTask *__restrict__ tab,
+                                                                      const int32_t *__restrict__ off, int ntask,
+                                                                      int total)
+{
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int t = task_of(off, ntask, b);
+        const GramTask tk = tab[t];
+        gram_core_body<J>(tk.rb, tk.ldrb, tk.kp, tk.ldkp, tk.nrows, tk.rows, tk.part, b - off[t]);
+        __syncthreads();   // the staged rows in LDS are reused by the next partial
+    }
+}
+
+// Rows per partial of the core Gram product (as gram_rows, TM waves a block).
+template <int J>
+static int gram_core_rows(int64_t nrows)
+{
+    int rows = kGramRows;
+    while (rows < 4096 && ((nrows + rows - 1) / rows) * gram_tm(J) > 2048) rows *= 2;
+    return rows;
+}
+
+// Position in the slab's Gram layout (rows and columns of width gram_width:
+// R x a at rows 0..J-1, columns 0..J-1; M x a a^T at rows and columns J..)
+// of cell q of a core Gram partial, or -1 for padding.
+template <int J>
+__device__ __forceinline__ int gram_core_dst(int q)
+{
+    constexpr int NM = gram_nm(J), MW = 16 * gram_tm(J), GW = gram_width(J);
+    if (q < MW * MW) {
+        const int i = q / MW, j = q % MW;
+        return (i < NM && j < NM) ? (J + i) * GW + J + j : -1;
+    }
+    const int i = (q - MW * MW) / 16, j = (q - MW * MW) % 16;
+    return (i < J && j < J) ? i * GW + j : -1;
+}
+
 // Fixed-order sum of the gram partials: block b owns outputs 64 b .. 64 b + 63;
 // wave w of the block sums partials w, w + 16, ... (coalesced across lanes),
 // then the 16 wave sums are added in wave order.
-__device__ __forceinline__ void gramsum_body(const double *__restrict__ part, int64_t nparts, int n,
-                                             double *__restrict__ out, int bx)
+template <typename Dst>
+__device__ __forceinline__ void gramsum_map_body(const double *__restrict__ part, int64_t nparts, int n,
+                                                 double *__restrict__ out, int bx, Dst dst)
 {
     __shared__ double sh[16][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -568,8 +731,15 @@ __device__ __forceinline__ void gramsum_body(const double *__restrict__ part, in
     if (w == 0 && q < n) {
         double t = 0.0;
         for (int i = 0; i < 16; ++i) t += sh[i][lane];
-        out[q] = t;
+        const int d = dst(q);
+        if (d >= 0) out[d] = t;
     }
+}
+
+__device__ __forceinline__ void gramsum_body(const double *__restrict__ part, int64_t nparts, int n,
+                                             double *__restrict__ out, int bx)
+{
+    gramsum_map_body(part, nparts, n, out, bx, [](int q) { return q; });
 }
 
 __global__ void __launch_bounds__(1024) k_gramsum(const double *__restrict__ part, int64_t nparts, int n,
@@ -585,14 +755,24 @@ struct GsumTask {
     double *out;
 };
 
-__global__ void __launch_bounds__(1024) k_gramsum_multi(const GsumTask *__restrict__ tab,
-                                                        const int32_t *__restrict__ off, int ntask, int total)
+// Sum of core Gram partials, written into the slab's Gram layout.
+template <int J>
+__global__ void __launch_bounds__(1024) k_gramsum_core(const double *__restrict__ part, int64_t nparts,
+                                                       double *__restrict__ out)
+{
+    gramsum_map_body(part, nparts, gram_core_cells(J), out, blockIdx.x, [](int q) { return gram_core_dst<J>(q); });
+}
+
+template <int J>
+__global__ void __launch_bounds__(1024) k_gramsum_core_multi(const GsumTask *__restrict__ tab,
+                                                             const int32_t *__restrict__ off, int ntask, int total)
 {
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int t = task_of(off, ntask, b);
         const GsumTask tk = tab[t];
-        gramsum_body(tk.part, tk.nparts, tk.n, tk.out, b - off[t]);
-        __syncthreads();   // the wave sums in LDS are reused by the next block of outputs
+        gramsum_map_body(tk.part, tk.nparts, gram_core_cells(J), tk.out, b - off[t],
+                         [](int q) { return gram_core_dst<J>(q); });
+        __syncthreads();
     }
 }
 
@@ -793,6 +973,63 @@ __global__ void __launch_bounds__(64) k_slabsolve_multi(const SolveTask *__restr
     }
 }
 
+// SSE after the core sweep without applying its last slab's change D to the
+// residual.  With e the residual the last slab's statistics were taken from,
+// rr and H that slab's right-hand side and Gram matrix:
+//   sum (e - sum_q D_q w_q)^2 = sum e^2 - 2 D . rr + D^T H D,
+// sum e^2 being the per-wave sums of the last slab pass.  Fixed summation
+// order (one block).
+__device__ __forceinline__ void sse_lag_body(const double *__restrict__ wsum, int nwaves, int J, int GW,
+                                             const double *__restrict__ gram, const double *__restrict__ dprev,
+                                             double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    const int B = J * J;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < nwaves; w += blockDim.x) s += wsum[w];
+    double qf = 0.0;
+    for (int q = threadIdx.x; q < B; q += blockDim.x) {
+        const double dq = dprev[q];
+        if (dq != 0.0) {
+            const int t = q / J, u = q % J;
+            double hd = 0.0;
+            for (int p = 0; p < B; ++p)
+                hd += gram[(J + symr(J, t, p / J)) * GW + J + symr(J, u, p % J)] * dprev[p];
+            qf += dq * (hd - 2.0 * gram[t * GW + u]);
+        }
+    }
+    const double S = block_sum(s, sh);
+    __syncthreads();
+    const double Q = block_sum(qf, sh);
+    if (threadIdx.x == 0) out[0] = S + Q;
+}
+
+template <int J>
+__global__ void __launch_bounds__(256) k_sse_lag(const double *__restrict__ wsum, int nwaves,
+                                                 const double *__restrict__ gram, const double *__restrict__ dprev,
+                                                 double *__restrict__ out)
+{
+    sse_lag_body(wsum, nwaves, J, gram_width(J), gram, dprev, out);
+}
+
+struct SseTask {
+    const double *wsum;
+    const double *gram;
+    const double *dprev;
+    double *out;
+    int32_t nwaves;
+};
+
+template <int J>
+__global__ void __launch_bounds__(256) k_sse_lag_multi(const SseTask *__restrict__ tab, int ntask)
+{
+    for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
+        const SseTask tk = tab[t];
+        sse_lag_body(tk.wsum, tk.nwaves, J, gram_width(J), tk.gram, tk.dprev, tk.out);
+        __syncthreads();
+    }
+}
+
 // Core keys of a batch of slabs: Delta(G_q) = 2 G_q sum e w_q + G_q^2 sum w_q^2 (Eq. 5).
 // sum w_q^2 comes from the batch product (WITH_D) or from the Gram diagonals
 // kept by the last core sweep.
@@ -878,11 +1115,16 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
     a.rowbuf = c->rowbuf;
     a.ldrb = c->ldrb;
     a.partials = partials;
+    a.wsum = c->wsum;
 
     const int blocks = (L.nwaves + 3) / 4;
-    const int grows = gram_rows<GW>(Ilast);
+    const int grows = gram_core_rows<J>(Ilast);
     const int64_t gchunks = (Ilast + grows - 1) / grows;
     const int nslab = ipow(J, N - 2);
+    // with more than one slab the last slab's change is not applied to the
+    // residual here (k_sse_lag forms the SSE); with one slab its statistics
+    // may come from the residual pass, which does not sum e^2
+    const bool lag = nslab > 1;
     auto digits = [&](int s, int32_t *out) {
         for (int m = N - 3; m >= 0; --m) {
             out[m] = s % J;
@@ -902,35 +1144,81 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
         digits(s, a.lead);
         a.has_prev = s > 0 ? 1 : 0;
         if (s > 0) digits(s - 1, a.lprev);
-        // the first slab's statistics may already come from the residual pass (OP_RESID_S0)
+        // the first slab's statistics may already come from the residual pass
+        // (OP_RESID_S0); the last slab's pass also sums e^2 (see k_sse_lag)
+        const bool lastp = lag && s == nslab - 1;
         if (!(s == 0 && slab0_done)) {
             const bool timed = c->slab_ev && c->slab_ev_n < c->slab_ev_cap;
             if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n], st);
-            if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, true>), dim3(blocks), dim3(256), 0, st, a);
+            if (blocks > 0) {
+                if (lastp)
+                    hipLaunchKernelGGL((k_slab<N, J, T, true, true>), dim3(blocks), dim3(256), 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_slab<N, J, T, true>), dim3(blocks), dim3(256), 0, st, a);
+            }
             if (timed) hipEventRecord(c->slab_ev[2 * c->slab_ev_n++ + 1], st);
         }
         if (L.nlong > 0)
             hipLaunchKernelGGL(k_slab_long<nacc_vc(J)>, dim3(L.nlong), dim3(64), 0, st, partials, L.longrows,
                                c->rowbuf, c->ldrb);
-        hipLaunchKernelGGL((k_gram<GW, GW>), dim3((unsigned)gchunks), dim3(gram_threads<GW>()), 0, st, c->rowbuf, c->ldrb, c->kp, GW,
-                           Ilast, grows, c->gram_part);
-        hipLaunchKernelGGL(k_gramsum, dim3((GW * GW + 63) / 64), dim3(1024), 0, st, c->gram_part, gchunks, GW * GW,
-                           c->gram);
+        hipLaunchKernelGGL(k_gram_core<J>, dim3((unsigned)gchunks), dim3(64 * gram_tm(J)), 0, st, c->rowbuf, c->ldrb,
+                           c->kp, GW, Ilast, grows, c->gram_part);
+        hipLaunchKernelGGL(k_gramsum_core<J>, dim3((gram_core_cells(J) + 63) / 64), dim3(1024), 0, st, c->gram_part,
+                           gchunks, c->gram);
         const int64_t base = (int64_t)s * J * J;
         hipLaunchKernelGGL(k_slabsolve<J>, dim3(1), dim3(64), 0, st, c->gram, c->core, c->cmask, base, c->d.lambda,
                            c->d.reg, c->dprev, c->hdiag);
+    }
+    if (lag) {
+        // the residual keeps lagging the last slab's change; its SSE is formed here
+        hipLaunchKernelGGL(k_sse_lag<J>, dim3(1), dim3(256), 0, st, c->wsum, L.nwaves, c->gram, c->dprev, c->sse_lag);
+        c->e_lag = true;
+        return hipGetLastError();
     }
     // apply the last slab's change to the residual
     a.has_prev = 1;
     digits(nslab - 1, a.lprev);
     if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, false>), dim3(blocks), dim3(256), 0, st, a);
+    c->e_lag = false;
+    return hipGetLastError();
+}
+
+// Apply the core sweep's last slab change (dprev) to a lagging residual.
+template <int N, int J, typename T>
+static hipError_t lag_apply_t(vest_ctx *c)
+{
+    const int last = N - 1;
+    const ModeLayout &L = c->lay[last];
+    SlabArgs<N, J, T> a{};
+    a.waves = L.waves;
+    a.nwaves = L.nwaves;
+    a.row_order = L.row_order;
+    for (int m = 0; m < N - 1; ++m) a.oidx[m] = L.oidx[m];
+    for (int m = 0; m < N - 2; ++m) {
+        a.colA[m] = reinterpret_cast<const T *>(c->colA[m]);   // column copies made by the core sweep
+        a.dimA[m] = c->d.dims[m];
+    }
+    a.ms = reinterpret_cast<const T *>(c->ms);
+    for (int m = 0; m < N - 2; ++m) a.rowA[m] = reinterpret_cast<const T *>(c->Ag[m]);
+    a.Alast = reinterpret_cast<const T *>(c->Ag[last]);
+    a.e = reinterpret_cast<T *>(c->e);
+    a.dprev = c->dprev;
+    a.has_prev = 1;
+    int s = ipow(J, N - 2) - 1;
+    for (int m = N - 3; m >= 0; --m) {
+        a.lprev[m] = s % J;
+        s /= J;
+    }
+    const int blocks = (L.nwaves + 3) / 4;
+    if (blocks > 0) hipLaunchKernelGGL((k_slab<N, J, T, false>), dim3(blocks), dim3(256), 0, c->stream, a);
     return hipGetLastError();
 }
 
 // The core sweep of several contexts of one shape, kernel by kernel as
 // core_pass_t launches it for one (slab passes, long-row sums, Gram product,
-// its sum and the sequential solve of every slab, then the last slab's
-// change applied to the residual), each launch carrying all the contexts.
+// its sum and the sequential solve of every slab, then the SSE of the lagging
+// residual, or with one slab its change applied), each launch carrying all
+// the contexts.
 template <int N, int J, typename T>
 static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_t st, BatchArena &ba, LaunchList &L)
 {
@@ -943,6 +1231,7 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
     std::vector<SlabLongTask> sl(n);
     std::vector<GramTask> gr(n);
     std::vector<GsumTask> gs(n);
+    std::vector<SseTask> sse(n);
     std::vector<int32_t> kpoff(n + 1, 0), coloff(1, 0), soff(n + 1, 0), sloff(n + 1, 0), groff(n + 1, 0),
         gsoff(n + 1, 0);
     for (int i = 0; i < n; ++i) {
@@ -970,17 +1259,19 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
         a.rowbuf = c->rowbuf;
         a.ldrb = c->ldrb;
         a.partials = c->partials;
+        a.wsum = c->wsum;
+        sse[i] = SseTask{c->wsum, c->gram, c->dprev, c->sse_lag, Ly.nwaves};
         kp[i] = KpTask{c->A[last], Ilast, GW, c->kp};
         kpoff[i + 1] = kpoff[i] + (int32_t)((Ilast + 255) / 256);
         soff[i + 1] = soff[i] + (Ly.nwaves + 3) / 4;
         sl[i] = SlabLongTask{c->partials, Ly.longrows, c->rowbuf, c->ldrb};
         sloff[i + 1] = sloff[i] + Ly.nlong;
-        const int grows = gram_rows<GW>(Ilast);
+        const int grows = gram_core_rows<J>(Ilast);
         const int64_t gchunks = (Ilast + grows - 1) / grows;
         gr[i] = GramTask{c->rowbuf, c->kp, c->gram_part, Ilast, c->ldrb, GW, grows};
         groff[i + 1] = groff[i] + (int32_t)gchunks;
-        gs[i] = GsumTask{c->gram_part, gchunks, GW * GW, c->gram};
-        gsoff[i + 1] = gsoff[i] + (GW * GW + 63) / 64;
+        gs[i] = GsumTask{c->gram_part, gchunks, gram_core_cells(J), c->gram};
+        gsoff[i + 1] = gsoff[i] + (gram_core_cells(J) + 63) / 64;
     }
     auto digits = [&](int s, int32_t *out) {
         for (int m = N - 3; m >= 0; --m) {
@@ -1018,7 +1309,9 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
     const size_t o_sl = ba.add(sl.data(), sizeof(SlabLongTask) * n), o_sloff = ba.add(sloff.data(), 4 * (n + 1));
     const size_t o_gr = ba.add(gr.data(), sizeof(GramTask) * n), o_groff = ba.add(groff.data(), 4 * (n + 1));
     const size_t o_gs = ba.add(gs.data(), sizeof(GsumTask) * n), o_gsoff = ba.add(gsoff.data(), 4 * (n + 1));
+    const size_t o_sse = ba.add(sse.data(), sizeof(SseTask) * n);
     if (ba.overflow) return false;
+    const bool lag = nslab > 1;   // as in core_pass_t
     const BatchArena B = ba;
     const int ncol = (int)col.size();
     const int tcol = coloff.back(), tkp = kpoff[n], tslab = soff[n], tsl = sloff[n], tgr = groff[n], tgs = gsoff[n];
@@ -1031,19 +1324,26 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
             hipLaunchKernelGGL(k_kp_multi<J>, dim3(grid(tkp)), dim3(256), 0, st, B.dptr<KpTask>(o_kp),
                                B.dptr<int32_t>(o_kpoff), n, tkp);
         for (int s = 0; s < nslab; ++s) {
-            if (!(s == 0 && fused) && tslab > 0)
-                hipLaunchKernelGGL((k_slab_multi<N, J, T, true>), dim3(grid(tslab)), dim3(256), 0, st,
-                                   B.dptr<SlabArgs<N, J, T>>(o_slab[s]), B.dptr<int32_t>(o_soff), n, tslab);
+            if (!(s == 0 && fused) && tslab > 0) {
+                if (lag && s == nslab - 1)
+                    hipLaunchKernelGGL((k_slab_multi<N, J, T, true, true>), dim3(grid(tslab)), dim3(256), 0, st,
+                                       B.dptr<SlabArgs<N, J, T>>(o_slab[s]), B.dptr<int32_t>(o_soff), n, tslab);
+                else
+                    hipLaunchKernelGGL((k_slab_multi<N, J, T, true>), dim3(grid(tslab)), dim3(256), 0, st,
+                                       B.dptr<SlabArgs<N, J, T>>(o_slab[s]), B.dptr<int32_t>(o_soff), n, tslab);
+            }
             if (tsl > 0)
                 hipLaunchKernelGGL(k_slab_long_multi<nacc_vc(J)>, dim3(grid(tsl)), dim3(64), 0, st,
                                    B.dptr<SlabLongTask>(o_sl), B.dptr<int32_t>(o_sloff), n, tsl);
-            hipLaunchKernelGGL((k_gram_multi<GW, GW>), dim3(grid(tgr)), dim3(gram_threads<GW>()), 0, st,
+            hipLaunchKernelGGL(k_gram_core_multi<J>, dim3(grid(tgr)), dim3(64 * gram_tm(J)), 0, st,
                                B.dptr<GramTask>(o_gr), B.dptr<int32_t>(o_groff), n, tgr);
-            hipLaunchKernelGGL(k_gramsum_multi, dim3(grid(tgs)), dim3(1024), 0, st, B.dptr<GsumTask>(o_gs),
+            hipLaunchKernelGGL(k_gramsum_core_multi<J>, dim3(grid(tgs)), dim3(1024), 0, st, B.dptr<GsumTask>(o_gs),
                                B.dptr<int32_t>(o_gsoff), n, tgs);
             hipLaunchKernelGGL(k_slabsolve_multi<J>, dim3(grid(n)), dim3(64), 0, st, B.dptr<SolveTask>(o_solve[s]), n);
         }
-        if (tslab > 0)
+        if (lag)
+            hipLaunchKernelGGL(k_sse_lag_multi<J>, dim3(grid(n)), dim3(256), 0, st, B.dptr<SseTask>(o_sse), n);
+        else if (tslab > 0)
             hipLaunchKernelGGL((k_slab_multi<N, J, T, false>), dim3(grid(tslab)), dim3(256), 0, st,
                                B.dptr<SlabArgs<N, J, T>>(o_final), B.dptr<int32_t>(o_soff), n, tslab);
     });
@@ -1081,6 +1381,14 @@ hipError_t launch_core_sweep(vest_ctx *c, bool slab0_done)
 hipError_t launch_core_keys(vest_ctx *c, double *core_key, hipStream_t st, double *partials)
 {
     return core_pass(c, true, core_key, false, st, partials);
+}
+hipError_t launch_lag_apply(vest_ctx *c)
+{
+#define VEST_CASE(NN, JJ) \
+    if (c->N == NN && c->J == JJ) return c->f32 ? lag_apply_t<NN, JJ, float>(c) : lag_apply_t<NN, JJ, double>(c);
+    VEST_SHAPES(VEST_CASE)
+#undef VEST_CASE
+    return hipErrorInvalidValue;
 }
 
 bool shape_supported(int N, int J)

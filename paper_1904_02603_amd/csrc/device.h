@@ -226,6 +226,18 @@ __device__ __forceinline__ void delta_vec2(const CoreBases<T> &G, const T (&ra)[
     pair_all<N - 1, J, T>(G, ra, rb, buf, acca, accb, da, db, std::make_integer_sequence<int, ipow(J, N - 1)>{});
 }
 
+// Sum over a block (blockDim.x a power of two) in a fixed LDS tree order.
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
 // Task of virtual block b in a launch that carries several contexts:
 // off[t] is the first virtual block of task t (off[0] = 0, nondecreasing);
 // the last task whose first block is <= b (tasks without blocks are skipped).

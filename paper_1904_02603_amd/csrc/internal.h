@@ -99,6 +99,13 @@ enum RowOp { OP_SWEEP = 0, OP_KEYS = 1, OP_RESID = 2, OP_RESID_S0 = 3 };
 __host__ __device__ constexpr int nacc_vc(int J) { return J * (J + 1) / 2 + J; }
 __host__ __device__ constexpr int round8(int x) { return (x + 7) / 8 * 8; }
 __host__ __device__ constexpr int gram_width(int J) { return round8(nacc_vc(J)); }
+// The core sweep's Gram product keeps two blocks of rb^T kp: the slab's
+// Gram matrix in symmetric-pair form (gram_nm x gram_nm, in 16 x 16 tiles,
+// gram_tm per side) and its right-hand side (one 16 x 16 tile); its partials
+// hold gram_core_cells values.
+__host__ __device__ constexpr int gram_nm(int J) { return J * (J + 1) / 2; }
+__host__ __device__ constexpr int gram_tm(int J) { return (gram_nm(J) + 15) / 16; }
+__host__ __device__ constexpr int gram_core_cells(int J) { return 256 * gram_tm(J) * gram_tm(J) + 256; }
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
@@ -202,6 +209,8 @@ struct vest_ctx {
     double *gram_part = nullptr;      // [nchunks][gw*gw]
     double *gram = nullptr;           // [gw*gw]
     double *dprev = nullptr;          // [J*J] last slab's core change
+    double *wsum = nullptr;           // [waves of the last mode] sum of e^2 per wave of the last slab pass
+    double *sse_lag = nullptr;        // SSE after the core sweep while e lags its last slab (device)
     double *partials = nullptr;       // long-row chunk partials
     double *partials_side = nullptr;  // ... of the core keys while they run on `side`
     void *gt = nullptr;               // gather-form core staging when it exceeds LDS (T, [o][j])
@@ -229,6 +238,10 @@ struct vest_ctx {
     uint64_t gp_version[VEST_MAX_ORDER] = {};
     bool ag_valid[VEST_MAX_ORDER] = {};
     bool e_valid = false;
+    // e lacks the change of the core sweep's last slab (held in dprev); the
+    // SSE it would have is in sse_lag, and the change is applied to e only
+    // when something reads e
+    bool e_lag = false;
     bool ms_valid = false;            // ms matches the current factors
     bool hdiag_valid = false;         // hdiag matches the current factors
     bool keys_pending = false;
@@ -264,7 +277,8 @@ hipError_t launch_compact(vest_ctx *c, int32_t **idx, double **val, int64_t *liv
 hipError_t launch_core_keys(vest_ctx *c, double *core_key, hipStream_t st, double *partials);
 hipError_t launch_permute_core(vest_ctx *c, int mode);
 hipError_t launch_gather_copy(vest_ctx *c, int mode);
-hipError_t launch_loss(vest_ctx *c, double *dev_out3);          // sse, reg (device)
+hipError_t launch_loss(vest_ctx *c, double *dev_out3, const double *sse);   // sse, reg (device); sse given or summed over e
+hipError_t launch_lag_apply(vest_ctx *c);   // apply the core sweep's last slab change to e
 hipError_t launch_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k);  // all tensors at once
 hipError_t launch_sumsq(hipStream_t s, const double *v, int64_t n, double *partial, double *out);
 hipError_t launch_mask_init(vest_ctx *c, int64_t *counts_dev);

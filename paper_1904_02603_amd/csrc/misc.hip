@@ -141,17 +141,6 @@ hipError_t launch_gather_copy(vest_ctx *c, int mode)
 // ------------------------------------------------------------- reductions
 // Deterministic sums: a fixed grid of kLossBlocks blocks, grid-stride order
 // per thread, a fixed LDS tree per block, then one block over the partials.
-__device__ __forceinline__ double block_sum(double v, double *sh)
-{
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    return sh[0];
-}
-
 template <typename T, int ABS>
 __global__ void __launch_bounds__(256) k_sum(const T *__restrict__ v, int64_t n, double *__restrict__ partial)
 {
@@ -167,8 +156,9 @@ __global__ void __launch_bounds__(256) k_sum(const T *__restrict__ v, int64_t n,
 
 // out[g] = sum over arrays a in group g of the kLossBlocks partials of a.
 // group_of[a] in {0, 1}; narr <= 16.
+// With sse given, out[0] is *sse instead of the group-0 sum.
 __global__ void __launch_bounds__(256) k_final(const double *__restrict__ partial, int narr, int ngroup0,
-                                               double *__restrict__ out)
+                                               double *__restrict__ out, const double *__restrict__ sse)
 {
     __shared__ double sh[256];
     double s0 = 0.0, s1 = 0.0;
@@ -182,7 +172,7 @@ __global__ void __launch_bounds__(256) k_final(const double *__restrict__ partia
     __syncthreads();
     const double t1 = block_sum(s1, sh);
     if (threadIdx.x == 0) {
-        out[0] = t0;
+        out[0] = sse ? *sse : t0;
         out[1] = t1;
     }
 }
@@ -190,18 +180,21 @@ __global__ void __launch_bounds__(256) k_final(const double *__restrict__ partia
 hipError_t launch_sumsq(hipStream_t s, const double *v, int64_t n, double *partial, double *out)
 {
     hipLaunchKernelGGL((k_sum<double, 0>), dim3(kLossBlocks), dim3(256), 0, s, v, n, partial);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partial, 1, 1, out);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partial, 1, 1, out, (const double *)nullptr);
     return hipGetLastError();
 }
 
-// dev_out[0] = SSE over the residual, dev_out[1] = sum of the regulariser
-// terms (squares for L_F, absolute values for L_1) over core and factors.
-hipError_t launch_loss(vest_ctx *c, double *dev_out)
+// dev_out[0] = SSE over the residual (or *sse, formed by the core sweep),
+// dev_out[1] = sum of the regulariser terms (squares for L_F, absolute values
+// for L_1) over core and factors.
+hipError_t launch_loss(vest_ctx *c, double *dev_out, const double *sse)
 {
     hipStream_t st = c->stream;
     double *part = c->red;
     const ModeLayout &L = c->lay[c->N - 1];
-    if (c->f32)
+    if (sse)
+        ;
+    else if (c->f32)
         hipLaunchKernelGGL((k_sum<float, 0>), dim3(kLossBlocks), dim3(256), 0, st,
                            reinterpret_cast<const float *>(c->e), L.nslots, part);
     else
@@ -218,7 +211,7 @@ hipError_t launch_loss(vest_ctx *c, double *dev_out)
     };
     reg(c->core, c->G);
     for (int n = 0; n < c->N; ++n) reg(c->A[n], c->d.dims[n] * c->J);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, part, a, 1, dev_out);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, st, part, a, 1, dev_out, sse);
     return hipGetLastError();
 }
 
