@@ -411,10 +411,12 @@ def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
     arrivals = np.cumsum(np.random.default_rng(SERVE_SEED).exponential(1.0 / rate, n_jobs))
     srv = vest.VestServer(arena_bytes, slots)
     r = run(srv, arrivals)
+    st_p = srv.stats()
     srv.close()
     # saturated: the whole stream queued at once (capacity of the server)
     srv = vest.VestServer(arena_bytes, slots)
     rs = run(srv, np.zeros(n_jobs))
+    st_s = srv.stats()
     srv.close()
     sat_rate = n_jobs / (rs[:, 2].max() - rs[:, 0].min())
     lat = r[:, 2] - r[:, 0]
@@ -429,7 +431,10 @@ def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
             "pool_entries": int(sum(t["idx"].shape[0] for t in tensors)),
             "job_entries_total": int(sum(tensors[j["tensor"]]["idx"].shape[0] for j in jobs)),
             "forms": forms, "orders": {str(o): sum(1 for j in jobs if len(j["ranks"]) == o) for o in (3, 4)},
-            "iterations_per_job": 10}
+            "iterations_per_job": 10,
+            "batched_iterations": {"poisson": st_p["batches"], "saturated": st_s["batches"]},
+            "jobs_per_batch": {"poisson": st_p["batched_job_iterations"] / max(1, st_p["batches"]),
+                               "saturated": st_s["batched_job_iterations"] / max(1, st_s["batches"])}}
 
 
 def gen_workload(name):

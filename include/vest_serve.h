@@ -22,8 +22,11 @@
  * else runs beside it.
  *
  * Threading: a server is driven by one host thread (vest_server_progress is
- * not re-entrant).  All host pointers of a job must stay valid until the job
- * has left the QUEUED state.
+ * not re-entrant).  The server runs two helper threads of its own that upload
+ * admitted jobs and build their layouts (vest_init, which waits for the job's
+ * stream), so the driving thread keeps enqueueing the other jobs' iterations
+ * meanwhile; a job stays QUEUED until that has finished.  All host
+ * pointers of a job must stay valid until the job has left the QUEUED state.
  */
 #ifndef VEST_SERVE_H
 #define VEST_SERVE_H
@@ -80,15 +83,18 @@ int vest_server_create(size_t device_bytes, int32_t slots, vest_server **out /* 
  * iteration count (checked as vest_init does, without touching the data). */
 int vest_server_submit(vest_server *s, const vest_job *job, int64_t *id /* host out */);
 
-/* One scheduling pass: retire jobs whose last iteration has completed,
- * enqueue the next iteration of every admitted job whose previous one has
- * completed, admit queued jobs that fit.  Waits for the GPU only inside the
- * admission (vest_init) and the retirement (result copies) of a job.
+/* One scheduling pass: retire jobs whose last iteration has completed, make
+ * active the jobs whose upload and vest_init a helper thread has finished,
+ * hand queued jobs that fit (arena blocks and a slot assigned here) to the
+ * helper threads, enqueue the next iteration of every active job whose
+ * previous one has completed.  Waits for the GPU only inside the retirement
+ * (loss and result copies) of a job.
  * *completed (may be NULL) receives the number of jobs retired by this pass. */
 int vest_server_progress(vest_server *s, int32_t *completed);
 
 /* State of a job and its times in seconds since the server was created:
- * times[0] arrival, times[1] admission, times[2] completion (-1 if not yet).
+ * times[0] arrival, times[1] admission (arena blocks and slot assigned),
+ * times[2] completion (-1 if not yet).
  * For a failed job *state is VEST_JOB_FAILED and *error the VEST_E* code. */
 int vest_server_status(vest_server *s, int64_t id, int32_t *state, int32_t *error, double times[3]);
 
@@ -98,7 +104,8 @@ int vest_server_status(vest_server *s, int64_t id, int32_t *state, int32_t *erro
  * the job has not finished (or was fetched already). */
 int vest_server_fetch(vest_server *s, int64_t id, double *const *factors, double *core, double *loss);
 
-/* out[0] queued, out[1] active, out[2] finished (not fetched), out[3] arena
+/* out[0] queued (with those being uploaded and initialised), out[1] active,
+ * out[2] finished (not fetched), out[3] arena
  * bytes in use, out[4] arena size, out[5] largest free block, out[6] batched
  * iterations issued, out[7] job-iterations they carried. */
 int vest_server_stats(vest_server *s, int64_t *out /* 8 values */);

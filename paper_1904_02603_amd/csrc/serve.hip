@@ -1,5 +1,8 @@
 // Request loop of libvest (include/vest_serve.h): admission by device
-// footprint into one arena, one stream per job slot; admitted jobs of one
+// footprint into one arena, one stream per job slot; a job's upload and
+// vest_init (layout build, which waits for its stream) run on an admission
+// worker thread while the progress thread keeps the other jobs' iterations
+// flowing; admitted jobs of one
 // class (order, rank, precision, entry count within a factor of 4) advance
 // together, one batched
 // iteration of Alg. 2 at a time (vest_iterate_many: every kernel of the
@@ -9,12 +12,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -107,6 +114,9 @@ struct Job {
     int slot = -1;
     int klass = -1;          // shape class (batched iterations), -1 until admitted
     int32_t iters_done = 0;
+    // admission on the worker thread: init_rc is valid once init_done is set
+    std::atomic<int> init_done{0};
+    int init_rc = 0;
     bool inflight = false;   // an iteration is enqueued and not yet complete
     bool in_batch = false;   // ... as part of its class's batch (else on its slot stream)
     // results (host)
@@ -163,6 +173,7 @@ struct Klass {
 };
 
 constexpr size_t kClassTable = 1u << 20;
+constexpr int kAdmissionThreads = 2;   // concurrent uploads + layout builds
 
 struct vest_server {
     char *base = nullptr;
@@ -175,8 +186,15 @@ struct vest_server {
     std::vector<int64_t> slot_job;   // job id per slot, -1 if free
     std::map<int64_t, std::unique_ptr<Job>> jobs;
     std::deque<int64_t> queue;
+    std::vector<int64_t> admitting;   // upload and vest_init in progress on the worker
     std::vector<int64_t> active;
     int64_t next_id = 1;
+    // admission workers: take jobs whose arena blocks and slot are assigned
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Job *> todo;
+    bool stop = false;
     int device = 0;
     std::chrono::steady_clock::time_point t0;
 
@@ -228,10 +246,9 @@ JobPtrs job_ptrs(vest_server *s, Job &j)
     return p;
 }
 
-// Allocate, upload and initialise a queued job in slot `slot`.  Returns
-// false (nothing held) if the arena cannot hold it now; on a hard error the
-// job is marked failed.
-bool admit(vest_server *s, Job &j, int slot)
+// Arena blocks of a queued job; false (nothing held) if the arena cannot
+// hold it now.  Progress thread.
+bool alloc_blocks(vest_server *s, Job &j)
 {
     for (int b = 0; b < 7; ++b) {
         j.blk[b].bytes = j.block_bytes(b);
@@ -241,6 +258,15 @@ bool admit(vest_server *s, Job &j, int slot)
         }
         j.blk[b].live = true;
     }
+    return true;
+}
+
+// Upload and initialise a job whose blocks and slot are assigned (worker
+// thread; touches only the job, its slot's stream and its arena blocks).
+// On failure the slot's stream is drained before returning.
+int init_job(vest_server *s, Job &j)
+{
+    const int slot = j.slot;
     hipStream_t st = s->streams[slot];
     JobPtrs p = job_ptrs(s, j);
     const vest_desc &d = j.in.desc;
@@ -255,25 +281,47 @@ bool admit(vest_server *s, Job &j, int slot)
     if (rc == VEST_OK)
         rc = vest_init(&d, st, (const int32_t *)s->ptr(j.blk[5]), (const double *)s->ptr(j.blk[6]), p.fac, p.core,
                        p.fmask, p.cmask, s->ptr(j.blk[0]), j.ws_bytes, &j.ctx);
-    // the observed tensor now lives in the workspace layouts
+    if (rc != VEST_OK) (void)hipStreamSynchronize(st);
+    return rc;
+}
+
+void admission_worker(vest_server *s)
+{
+    (void)hipSetDevice(s->device);   // the current device is per host thread
+    for (;;) {
+        Job *j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [&] { return s->stop || !s->todo.empty(); });
+            if (s->stop) return;
+            j = s->todo.front();
+            s->todo.pop_front();
+        }
+        j->init_rc = init_job(s, *j);
+        j->init_done.store(1, std::memory_order_release);
+    }
+}
+
+// A job the worker has finished with: the observed tensor now lives in the
+// workspace layouts (vest_init waited for its stream), so its blocks go back
+// to the arena; the job becomes active or fails.  Progress thread.
+void finish_admission(vest_server *s, Job &j)
+{
     for (int b = 5; b < 7; ++b)
         if (j.blk[b].live) {
             s->arena.release(j.blk[b].off, j.blk[b].bytes);
             j.blk[b].live = false;
         }
-    j.t_admit = s->now();
-    if (rc != VEST_OK) {
-        hipStreamSynchronize(st);
+    if (j.init_rc != VEST_OK) {
         release_blocks(s, j);
+        s->slot_job[j.slot] = -1;
+        j.slot = -1;
         j.state = VEST_JOB_FAILED;
-        j.error = rc;
+        j.error = j.init_rc;
         j.t_done = s->now();
-        return true;
+        return;
     }
-    j.slot = slot;
-    s->slot_job[slot] = j.id;
     j.state = VEST_JOB_ACTIVE;
-    return true;
 }
 
 // Jobs of a class advance in lockstep, so a class also bounds the spread of
@@ -428,6 +476,13 @@ int vest_server_create(size_t device_bytes, int32_t slots, vest_server **out)
         vest_server_destroy(s);
         return hip_fail(e, "server streams");
     }
+    try {
+        for (int w = 0; w < kAdmissionThreads; ++w) s->workers.emplace_back(admission_worker, s);
+    } catch (...) {
+        vest_server_destroy(s);
+        set_error("cannot start the admission thread");
+        return VEST_EINVAL;
+    }
     *out = s;
     return VEST_OK;
 }
@@ -505,31 +560,48 @@ int vest_server_progress(vest_server *s, int32_t *completed)
         still.push_back(id);
     }
     s->active.swap(still);
-    // 3. admit queued jobs in arrival order; later jobs fill in when the head
-    //    does not fit yet
-    for (auto it = s->queue.begin(); it != s->queue.end();) {
-        int slot = -1;
-        for (size_t k = 0; k < s->slot_job.size(); ++k)
-            if (s->slot_job[k] < 0) { slot = (int)k; break; }
-        if (slot < 0) break;
-        Job &j = *s->jobs[*it];
-        if (j.footprint() > s->arena.size() - s->arena.used()) {
-            ++it;
+    // 3. admissions the worker finished
+    std::vector<int64_t> pending;
+    for (int64_t id : s->admitting) {
+        Job &j = *s->jobs[id];
+        if (!j.init_done.load(std::memory_order_acquire)) {
+            pending.push_back(id);
             continue;
         }
-        if (!admit(s, j, slot)) {
-            ++it;
-            continue;
-        }
+        finish_admission(s, j);
         if (j.state == VEST_JOB_ACTIVE) {
             j.klass = klass_of(s, j);
             s->active.push_back(j.id);
         } else {
             ++done;  // failed at admission
         }
+    }
+    s->admitting.swap(pending);
+    // 4. admit queued jobs in arrival order (later jobs fill in when the head
+    //    does not fit yet): blocks and slot here, upload and vest_init on the
+    //    worker
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+        int slot = -1;
+        for (size_t k = 0; k < s->slot_job.size(); ++k)
+            if (s->slot_job[k] < 0) { slot = (int)k; break; }
+        if (slot < 0) break;
+        Job &j = *s->jobs[*it];
+        if (j.footprint() > s->arena.size() - s->arena.used() || !alloc_blocks(s, j)) {
+            ++it;
+            continue;
+        }
+        j.slot = slot;
+        s->slot_job[slot] = j.id;
+        j.t_admit = s->now();
+        s->admitting.push_back(j.id);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->todo.push_back(&j);
+        }
+        s->cv.notify_one();
         it = s->queue.erase(it);
     }
-    // 4. the next iteration of every idle job, batched per class
+    // 5. the next iteration of every idle job, batched per class
     for (size_t k = 0; k < s->classes.size(); ++k) {
         std::vector<int64_t> failed = enqueue_class(s, (int)k);
         if (failed.empty()) continue;
@@ -594,7 +666,7 @@ int vest_server_stats(vest_server *s, int64_t *out)
     int64_t finished = 0;
     for (auto &kv : s->jobs)
         if (kv.second->state == VEST_JOB_DONE && !kv.second->fetched) ++finished;
-    out[0] = (int64_t)s->queue.size();
+    out[0] = (int64_t)(s->queue.size() + s->admitting.size());
     out[1] = (int64_t)s->active.size();
     out[2] = finished;
     out[3] = (int64_t)s->arena.used();
@@ -608,6 +680,18 @@ int vest_server_stats(vest_server *s, int64_t *out)
 int vest_server_destroy(vest_server *s)
 {
     if (!s) return VEST_OK;
+    {   // admissions in progress complete first
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    for (std::thread &t : s->workers)
+        if (t.joinable()) t.join();
+    for (int64_t id : s->admitting) {
+        Job &j = *s->jobs[id];
+        if (j.init_done.load(std::memory_order_acquire) && j.ctx) vest_destroy(j.ctx);
+        j.ctx = nullptr;
+    }
     for (hipStream_t st : s->streams)
         if (st) hipStreamSynchronize(st);
     for (Klass &K : s->classes)
