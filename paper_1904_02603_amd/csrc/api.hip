@@ -150,7 +150,7 @@ static bool carve(vest_ctx *c, const Plan &p, Bump &b, char **scratch)
     c->hdiag = (double *)take(c->G * 8);
     for (int n = 0; n < N; ++n) c->Gp[n] = take(c->G * ts);
     for (int n = 0; n < N; ++n) c->Ag[n] = take(c->d.dims[n] * gather_ld(J, (int)ts) * ts);
-    for (int m = 0; m + 2 < N; ++m) c->colA[m] = take(c->d.dims[m] * J * ts);
+    for (int m = 0; m + 2 < N; ++m) c->colA[m] = take(c->d.dims[m] * J * ts * (N == 3 ? 2 : 1));   // order 3: pairs
     const int gw = gram_width(J);
     const int64_t Il = c->d.dims[N - 1];
     c->ldrb = rowbuf_width(N, J, (int)ts);

@@ -37,7 +37,8 @@ struct SlabArgs {
     int32_t has_prev;
     const int32_t *row_order;
     const int32_t *oidx[N - 1];   // core layout: modes 0..N-2
-    const T *colA[NL];            // column-major copies of modes 0..N-3
+    const T *colA[NL];            // column-major copies of modes 0..N-3; at order 3 column pairs
+                                  // (a_{i,s-1}, a_{i,s}) of mode 0 (see colcopy_body)
     const T *rowA[NL];            // gather copies of modes 0..N-3 (row stride gather_ld)
     int64_t dimA[NL];
     int32_t lead[NL];             // leading core indices of this slab
@@ -130,11 +131,22 @@ __device__ __forceinline__ void slab_body(const SlabArgs<N, J, T> &a, int bx)
         for (int q = 0; q < U; ++q) {
             ok[q] = (k0 + q < wi.K) && ii[q][0] >= 0;
             T pv = T(1), pr = T(1);
+            if constexpr (N == 3) {
+                // one aligned pair load: (a_{i,s-1}, a_{i,s}) of slab s = lead, whose previous
+                // slab is s - 1; the apply-only pass reads the pair of the previous slab
+                const int64_t i = ii[q][0] > 0 ? ii[q][0] : 0;
+                const int64_t c = ACC ? a.lead[0] : a.lprev[0];
+                typedef T t2 __attribute__((ext_vector_type(2)));
+                const t2 pair = *reinterpret_cast<const t2 *>(a.colA[0] + 2 * (c * a.dimA[0] + i));
+                if constexpr (ACC) pv = pair.y;
+                if (a.has_prev) pr = ACC ? pair.x : pair.y;
+            } else {
 #pragma unroll
-            for (int m = 0; m < N - 2; ++m) {
-                const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
-                if constexpr (ACC) pv *= a.colA[m][(int64_t)a.lead[m] * a.dimA[m] + i];
-                if (a.has_prev) pr *= a.colA[m][(int64_t)a.lprev[m] * a.dimA[m] + i];
+                for (int m = 0; m < N - 2; ++m) {
+                    const int64_t i = ii[q][m] > 0 ? ii[q][m] : 0;
+                    if constexpr (ACC) pv *= a.colA[m][(int64_t)a.lead[m] * a.dimA[m] + i];
+                    if (a.has_prev) pr *= a.colA[m][(int64_t)a.lprev[m] * a.dimA[m] + i];
+                }
             }
             p[q] = ok[q] ? pv : T(0);
             pp[q] = ok[q] ? pr : T(0);
@@ -409,19 +421,31 @@ __global__ void __launch_bounds__(256) k_kp2(const double *__restrict__ A, int64
     for (int v = 2 * J; v < w; ++v) d[v] = 0.0;
 }
 
+// Column-major copy of a leading factor for the core passes: out[j I + i] =
+// a_{i j}.  With pair set (order 3, one leading mode, whose slabs s run in
+// order) column s holds the pairs (a_{i,s-1}, a_{i,s}) -- a_{i,0} twice for
+// s = 0 -- so that a slab pass reads both leading values of an entry with one
+// aligned load: out[2 (s I + i) + {0, 1}].
 template <typename T>
-__device__ __forceinline__ void colcopy_body(const double *__restrict__ A, int64_t I, int J, T *__restrict__ out, int bx)
+__device__ __forceinline__ void colcopy_body(const double *__restrict__ A, int64_t I, int J, int pair,
+                                             T *__restrict__ out, int bx)
 {
     const int64_t q = (int64_t)bx * blockDim.x + threadIdx.x;
     if (q >= I * J) return;
     const int64_t j = q / I, i = q % I;
-    out[q] = (T)A[i * J + j];
+    if (pair) {
+        out[2 * q] = (T)A[i * J + (j > 0 ? j - 1 : 0)];
+        out[2 * q + 1] = (T)A[i * J + j];
+    } else {
+        out[q] = (T)A[i * J + j];
+    }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, int64_t I, int J, T *__restrict__ out)
+__global__ void __launch_bounds__(256) k_colcopy(const double *__restrict__ A, int64_t I, int J, int pair,
+                                                 T *__restrict__ out)
 {
-    colcopy_body<T>(A, I, J, out, blockIdx.x);
+    colcopy_body<T>(A, I, J, pair, out, blockIdx.x);
 }
 
 template <typename T>
@@ -429,6 +453,7 @@ struct ColTask {
     const double *A;
     int64_t I;
     int32_t J;
+    int32_t pair;
     T *out;
 };
 
@@ -439,7 +464,7 @@ __global__ void __launch_bounds__(256) k_colcopy_multi(const ColTask<T> *__restr
     for (int b = blockIdx.x; b < total; b += gridDim.x) {
         const int t = task_of(off, ntask, b);
         const ColTask<T> tk = tab[t];
-        colcopy_body<T>(tk.A, tk.I, tk.J, tk.out, b - off[t]);
+        colcopy_body<T>(tk.A, tk.I, tk.J, tk.pair, tk.out, b - off[t]);
     }
 }
 
@@ -1103,7 +1128,7 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
     for (int m = 0; m < N - 2; ++m) {
         const int64_t I = c->d.dims[m];
         hipLaunchKernelGGL(k_colcopy<T>, dim3((unsigned)((I * J + 255) / 256)), dim3(256), 0, st, c->A[m], I, J,
-                           reinterpret_cast<T *>(c->colA[m]));
+                           N == 3 ? 1 : 0, reinterpret_cast<T *>(c->colA[m]));
         a.colA[m] = reinterpret_cast<const T *>(c->colA[m]);
         a.dimA[m] = I;
     }
@@ -1246,7 +1271,7 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
         for (int m = 0; m < N - 1; ++m) a.oidx[m] = Ly.oidx[m];
         for (int m = 0; m < N - 2; ++m) {
             const int64_t I = c->d.dims[m];
-            col.push_back(ColTask<T>{c->A[m], I, J, reinterpret_cast<T *>(c->colA[m])});
+            col.push_back(ColTask<T>{c->A[m], I, J, N == 3 ? 1 : 0, reinterpret_cast<T *>(c->colA[m])});
             coloff.push_back(coloff.back() + (int32_t)((I * J + 255) / 256));
             a.colA[m] = reinterpret_cast<const T *>(c->colA[m]);
             a.dimA[m] = I;

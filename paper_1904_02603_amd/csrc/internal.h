@@ -202,7 +202,7 @@ struct vest_ctx {
     double *hdiag = nullptr;          // diagonal of every slab's Gram matrix [|G|]
     void *Gp[VEST_MAX_ORDER] = {};    // core permuted for each mode (T)
     void *Ag[VEST_MAX_ORDER] = {};    // gather copies of the factors (T, row stride gather_ld)
-    void *colA[VEST_MAX_ORDER] = {};  // column-major factor copies, modes < N-2 (T)
+    void *colA[VEST_MAX_ORDER] = {};  // column-major factor copies, modes < N-2 (T; order 3: column pairs)
     double *rowbuf = nullptr;         // [I_{N-1}][ldrb]
     int ldrb = 0;
     double *kp = nullptr;             // [I_{N-1}][gram_width]
