@@ -87,14 +87,18 @@ int plan_workspace(const vest_desc *d, Plan *p)
     maxt = G > maxt ? G : maxt;
     p->max_tensor = maxt;
     for (int n = 0; n < N; ++n) {
-        // class-c waves (c >= 1) hold rows longer than kLaneTarget 2^(c-1):
-        // at most 2 nnz / (64 kLaneTarget) + 1 waves per class; long rows add
-        // at most 2 nnz / kChunk chunk waves
-        p->slot_bound[n] = nnz + nnz / 8 + 1024 * kLaneTarget + 1024;
-        p->wave_bound[n] = d->dims[n] / 64 + nnz / (32 * kLaneTarget) + 2 * nnz / kChunk + 16;
-        p->long_bound[n] = nnz / kChunk + 1;
+        // class-c waves (c >= 1) hold rows longer than LT 2^(c-1): at most
+        // 2 nnz / (64 LT) + 1 waves per class; long rows add at most
+        // 2 nnz / (64 LT) chunk waves
+        // rounding pads a row of L entries by less than 2 L / LT slots, each
+        // length class's last wave by at most 64 LT; the wave and chunk
+        // counts are bounded at the smaller target (both layouts fit)
+        const int64_t lt = lane_target_for(nnz), ch = (int64_t)kWave * kLaneTargetSmall;
+        p->slot_bound[n] = nnz + 2 * nnz / lt + 1024 * lt + 1024;
+        p->wave_bound[n] = d->dims[n] / 64 + nnz / (32 * kLaneTargetSmall) + 2 * nnz / ch + 16;
+        p->long_bound[n] = nnz / ch + 1;
     }
-    p->chunk_bound = 2 * nnz / kChunk + 1;
+    p->chunk_bound = 2 * nnz / ((int64_t)kWave * kLaneTargetSmall) + 1;
     p->gram_chunks = (d->dims[N - 1] + kGramRows - 1) / kGramRows;
     size_t t1 = 0, t2 = 0;
     hipError_t e1 = hipcub::DeviceRadixSort::SortPairs(nullptr, t1, (uint32_t *)nullptr, (uint32_t *)nullptr,

@@ -5,11 +5,12 @@
 //  * Per mode n, a "row-group" layout of Omega grouped by the mode-n index
 //    (Omega^{(n)}_{i_n}, Table 1).  Rows are grouped into classes by length:
 //    a row of L entries gets g = 2^c lanes of one 64-lane wavefront, the
-//    smallest power of two with ceil(L / g) <= kLaneTarget; 64/g rows share a
-//    wave.  Inside a class rows are ordered by decreasing length, so the lanes
-//    of a wave carry nearly equal work.  Rows longer than 64 * kLaneTarget are
-//    cut into chunks of 64 * kLaneTarget entries, one wave each, whose partial
-//    sums are combined in a fixed order by a finishing kernel.
+//    smallest power of two with ceil(L / g) <= LT (the layout's lane target,
+//    lane_target_for); 64/g rows share a wave.  Inside a class rows are
+//    ordered by decreasing length, so the lanes of a wave carry nearly equal
+//    work.  Rows longer than 64 LT are cut into chunks of 64 LT entries, one
+//    wave each, whose partial sums are combined in a fixed order by a
+//    finishing kernel.
 //    Entry (k, lane) of wave w lives in slot waves[w].base + 64 k + lane, so
 //    the k-th entries of the 64 lanes are contiguous: every index / value load
 //    of a wave is one coalesced 256-byte (or 512-byte) transaction.  Lane l of
@@ -47,8 +48,14 @@ __host__ __device__ constexpr bool dense_form(int N, int J) { return J > 0 && de
 namespace vest {
 
 constexpr int kWave = 64;
-constexpr int kLaneTarget = 16;                   // entries per lane in a row group
-constexpr int kChunk = kWave * kLaneTarget;       // entries per long-row chunk
+// Entries per lane of a row group (the layout's lane target LT): 16 from 2^22
+// entries, 8 below, where the shorter per-wave loops and the extra waves pay
+// (measured: 16 best at 10^7 entries, 8 up to 30 % faster on 10^6-entry and
+// compacted sets).  Rows longer than 64 LT entries are cut into chunks of
+// 64 LT.  Workspace bounds hold for both targets.
+constexpr int kLaneTargetSmall = 8, kLaneTargetLarge = 16;
+constexpr int64_t kLaneTargetLargeFrom = int64_t(1) << 22;
+inline int lane_target_for(int64_t nnz) { return nnz >= kLaneTargetLargeFrom ? kLaneTargetLarge : kLaneTargetSmall; }
 constexpr int kGramRows = 128;                    // rows per gram partial
 constexpr int kLossBlocks = 1024;                 // fixed grid of the loss reductions
 constexpr int64_t kSideStreamMinNnz = 1 << 20;    // entries from which the key passes overlap
@@ -82,6 +89,7 @@ struct ModeLayout {
     int32_t nlong = 0;
     int32_t nchunks = 0;
     int64_t maxlen = 0;
+    int32_t lane_target = kLaneTargetLarge;   // LT of the current layout
     WaveInfo *waves = nullptr;
     int32_t *row_order = nullptr;
     int32_t *oidx[VEST_MAX_ORDER] = {};

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_scatter(const uint32_t *__restrict__ ro
                                                  const RowPlace *__restrict__ place, const WaveInfo *__restrict__ waves,
                                                  const int32_t *__restrict__ idx, int N, int mode,
                                                  const double *__restrict__ val, OidxArg oidx, T *__restrict__ xval,
-                                                 int32_t *__restrict__ perm)
+                                                 int32_t *__restrict__ perm, int chunk)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nnz) return;
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) k_scatter(const uint32_t *__restrict__ ro
         const int64_t g = 1ll << P.glog;
         slot = P.base + (q >> P.glog) * kWave + ((int64_t)P.sub << P.glog) + (q & (g - 1));
     } else {
-        slot = waves[P.base + q / kChunk].base + (q % kChunk);
+        slot = waves[P.base + q / chunk].base + (q % chunk);
     }
     int m = 0;
     for (int k = 0; k < N; ++k) {
@@ -157,19 +157,20 @@ struct HostPlan {
     int32_t nchunks = 0;
 };
 
-static void plan_mode(const std::vector<uint32_t> &cnt, HostPlan &hp)
+static void plan_mode(const std::vector<uint32_t> &cnt, int lt, HostPlan &hp)
 {
     const int64_t I = (int64_t)cnt.size();
+    const int64_t chunk = (int64_t)kWave * lt;   // long-row chunk
     std::vector<int32_t> cls[7], longs;
     for (int64_t r = 0; r < I; ++r) {
         const int64_t len = cnt[r];
         hp.maxlen = std::max<int64_t>(hp.maxlen, len);
-        if (len > kChunk) {
+        if (len > chunk) {
             longs.push_back((int32_t)r);
             continue;
         }
         int c = 0;
-        while (((len + (int64_t(1) << c) - 1) >> c) > kLaneTarget) ++c;
+        while (((len + (int64_t(1) << c) - 1) >> c) > lt) ++c;
         cls[c].push_back((int32_t)r);
     }
     auto by_len = [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; };
@@ -205,13 +206,13 @@ static void plan_mode(const std::vector<uint32_t> &cnt, HostPlan &hp)
     }
     for (int32_t r : longs) {
         const int64_t len = cnt[r];
-        const int32_t nch = (int32_t)((len + kChunk - 1) / kChunk);
+        const int32_t nch = (int32_t)((len + chunk - 1) / chunk);
         hp.place[r] = RowPlace{(int64_t)hp.waves.size(), -1, 0};
         hp.longrows.push_back(LongRow{r, hp.nchunks, nch, 0});
         const int32_t pos = (int32_t)hp.row_order.size();
         hp.row_order.push_back(r);
         for (int32_t ch = 0; ch < nch; ++ch) {
-            const int64_t n = std::min<int64_t>(kChunk, len - (int64_t)ch * kChunk);
+            const int64_t n = std::min<int64_t>(chunk, len - (int64_t)ch * chunk);
             WaveInfo w{};
             w.base = slot;
             w.K = (int32_t)((n + kWave - 1) / kWave);
@@ -291,11 +292,19 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
         CHECK_HIP(hipStreamSynchronize(st));
 
         HostPlan hp;
-        plan_mode(cnt, hp);
-        if (hp.nslots > L.cap_slots || (int64_t)hp.waves.size() > L.cap_waves ||
-            (int64_t)hp.longrows.size() > L.cap_long || hp.nchunks > L.cap_chunks) {
-            return hipErrorOutOfMemory;
+        auto fits = [&] {
+            return hp.nslots <= L.cap_slots && (int64_t)hp.waves.size() <= L.cap_waves &&
+                   (int64_t)hp.longrows.size() <= L.cap_long && hp.nchunks <= L.cap_chunks;
+        };
+        int lt = lane_target_for(nnz);
+        plan_mode(cnt, lt, hp);
+        if (!fits() && lt != kLaneTargetLarge) {   // a compaction of a context sized for the larger target
+            hp = HostPlan();
+            lt = kLaneTargetLarge;
+            plan_mode(cnt, lt, hp);
         }
+        if (!fits()) return hipErrorOutOfMemory;
+        L.lane_target = lt;
         L.nslots = hp.nslots;
         L.npad = hp.nslots - nnz;
         L.nwaves = (int32_t)hp.waves.size();
@@ -321,10 +330,12 @@ hipError_t build_layouts(vest_ctx *c, const int32_t *idx, const double *val, cha
         for (int m = 0; m < N - 1; ++m) oa.p[m] = L.oidx[m];
         if (c->f32)
             hipLaunchKernelGGL(k_scatter<float>, dim3(grid_for(nnz)), dim3(256), 0, st, kb, vb, nnz, rptr, place,
-                               L.waves, idx, N, n, val, oa, reinterpret_cast<float *>(L.xval), L.perm);
+                               L.waves, idx, N, n, val, oa, reinterpret_cast<float *>(L.xval), L.perm,
+                               kWave * lt);
         else
             hipLaunchKernelGGL(k_scatter<double>, dim3(grid_for(nnz)), dim3(256), 0, st, kb, vb, nnz, rptr, place,
-                               L.waves, idx, N, n, val, oa, reinterpret_cast<double *>(L.xval), L.perm);
+                               L.waves, idx, N, n, val, oa, reinterpret_cast<double *>(L.xval), L.perm,
+                               kWave * lt);
         CHECK_HIP(hipGetLastError());
         // the host vectors above are read by pending copies: wait before reuse
         CHECK_HIP(hipStreamSynchronize(st));
