@@ -43,8 +43,15 @@ def masks_equal(g, o, what):
 @pytest.mark.parametrize("reg", [REG_LF, REG_L1], ids=["LF", "L1"])
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_ranks_iteration_keys_prune(case, reg):
+    """Where the core has at least as many elements as there are entries
+    (order 4 at ranks 9 and 10 here) the core sweep solves an underdetermined
+    system and amplifies rounding-order differences from one step to the next
+    (as at order 10, test_gpu_orders); there every step starts from the
+    oracle's state, so the element-wise bar applies to each step."""
+    from test_gpu_orders import resync
     dims, ranks, nnz = case
-    say("case", dims, ranks, nnz, reg)
+    stepwise = int(np.prod(ranks)) >= nnz
+    say("case", dims, ranks, nnz, reg, "stepwise" if stepwise else "")
     p = make(dims, ranks, nnz, 101)
     rng = np.random.default_rng(102)
     fmask = [(rng.random((d, r)) < 0.05).astype(np.uint8) for d, r in zip(dims, ranks)]
@@ -52,6 +59,8 @@ def test_ranks_iteration_keys_prune(case, reg):
     lam = 0.05 if reg == REG_LF else 0.3
     g, o = pair(p, reg, lam, fmask=fmask, cmask=cmask)
     for it in range(2):
+        if stepwise and it > 0:
+            g = resync(o, reg, lam, p)
         g.iteration()
         o.iteration()
         assert_state(g, o, what="iteration %d" % it)
@@ -69,6 +78,8 @@ def test_ranks_iteration_keys_prune(case, reg):
     o.prune(ock, ofk, ck, fk)
     masks_equal(g, o, "after prune")
     assert_state(g, o, what="after prune")
+    if stepwise:
+        g = resync(o, reg, lam, p)
     g.iteration()
     o.iteration()
     assert_state(g, o, what="iteration after prune")
