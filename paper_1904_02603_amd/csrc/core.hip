@@ -819,16 +819,20 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sequential updates of one slab's unpruned elements in flat order, one
-// wave.  Lane l holds, for the elements q = l, l + 64, ..., the running
-// correction sum_{p<q} H_qp D_p, which the sequential chain reads with
-// readlane; the element constants (core value, rr_q, H_qq, reciprocal of the
-// denominator) are LDS broadcasts, and H lives in LDS.  The diagonal of H is
-// kept (it is sum w_q^2, reused by the core keys).
-template <int J>
+// Sequential updates of one slab's unmarked elements in flat order, one
+// wave.  Lane l owns the elements q = l, l + 64, ...: it holds their
+// constants (core value, rr_q, H_qq, reciprocal of the denominator), their
+// running correction sum_{p<q} H_qp D_p and, once updated, their new value
+// and change.  Element q's values reach the chain by readlane from the owner
+// lane; the constants do not depend on the chain, so only the correction's
+// read sits on it.  H lives in LDS; the column for the next element is read
+// one element ahead.  A marked element goes through the same arithmetic with
+// its change forced to zero (selects, no branch).  The diagonal of H is kept
+// (it is sum w_q^2, reused by the core keys).
+template <int J, int REG>
 __device__ __forceinline__ void slabsolve_body(const double *__restrict__ gram, double *__restrict__ core,
                                                const uint8_t *__restrict__ cmask, int64_t base, double lambda,
-                                               int reg, double *__restrict__ dprev, double *__restrict__ hdiag)
+                                               double *__restrict__ dprev, double *__restrict__ hdiag)
 {
     constexpr int GW = gram_width(J);
     constexpr int B = J * J;
@@ -854,36 +858,28 @@ __device__ __forceinline__ void slabsolve_body(const double *__restrict__ gram, 
     auto H = [&](int q, int q2) {
         return sg[(J + symr(J, q / J, q2 / J)) * GW + J + symr(J, q % J, q2 % J)];
     };
-    // per element: core value, rr, H_qq and the reciprocal of the
-    // denominator, read by every lane as LDS broadcasts; the element's new
-    // value and change, written by its owner lane when it is updated
-    __shared__ double ec[4][B], eo[2][B];
-    double corr[CPL];
+    double eg[CPL], er[CPL], eh[CPL], eiq[CPL], corr[CPL], nwv[CPL], dqv[CPL];
     uint64_t mbits[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int q = lane + c * kWave;
         const bool in = q < B;
         const double h = in ? H(q, q) : 0.0;
+        eg[c] = in ? core[base + q] : 0.0;
+        er[c] = in ? sg[(q / J) * GW + (q % J)] : 0.0;
+        eh[c] = h;
+        eiq[c] = REG == VEST_REG_LF ? 1.0 / (h + lambda) : (h > 0.0 ? 1.0 / (2.0 * h) : 0.0);
         corr[c] = 0.0;
+        nwv[c] = eg[c];
+        dqv[c] = 0.0;
         mbits[c] = __ballot(in && cmask[base + q] != 0);
-        if (in) {
-            const double g = core[base + q];
-            ec[0][q] = g;
-            ec[1][q] = sg[(q / J) * GW + (q % J)];
-            ec[2][q] = h;
-            ec[3][q] = reg == VEST_REG_LF ? 1.0 / (h + lambda) : (h > 0.0 ? 1.0 / (2.0 * h) : 0.0);
-            eo[0][q] = g;
-            eo[1][q] = 0.0;
-            hdiag[base + q] = h;
-        }
+        if (in) hdiag[base + q] = h;
     }
-    __syncthreads();
     // H(q2, q) for the lane's elements q2 = lane + 64 c, q = t J + u: the LDS
     // index is a per-lane row base for (t2, t), formed once per t, plus a
     // per-lane column offset for (u2, u), tabulated for every u; the loop over
-    // u is unrolled so that the table index is a constant.  The reads for
-    // element q + 1 are issued before the dependent chain of element q.
+    // u is unrolled so that the table index is a constant.  Out-of-range
+    // pairs read cell 0 and are zeroed by a select.
     int t2[CPL], bcol[CPL][J];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
@@ -901,7 +897,9 @@ __device__ __forceinline__ void slabsolve_body(const double *__restrict__ gram, 
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int q2 = lane + c * kWave;
-            hc[c] = (q2 < B && q < B) ? sg[ra[c] + bcol[c][u]] : 0.0;
+            const bool ok = q2 < B && q < B;
+            const double x = sg[ok ? ra[c] + bcol[c][u] : 0];
+            hc[c] = ok ? x : 0.0;
         }
     };
     int ra[CPL];
@@ -921,35 +919,40 @@ __device__ __forceinline__ void slabsolve_body(const double *__restrict__ gram, 
                 hcol(rn, 0, q + 1, hnxt);
             const int oc = q / kWave, ol = q % kWave;
             uint64_t mb = mbits[0];
-            double cc = corr[0];
+            double vg = eg[0], vr = er[0], vh = eh[0], vi = eiq[0], vc = corr[0];
 #pragma unroll
             for (int c = 1; c < CPL; ++c)
                 if (oc == c) {
                     mb = mbits[c];
-                    cc = corr[c];
+                    vg = eg[c];
+                    vr = er[c];
+                    vh = eh[c];
+                    vi = eiq[c];
+                    vc = corr[c];
                 }
-            if (!((mb >> ol) & 1ull)) {
-                const double g = ec[0][q], r = ec[1][q], h = ec[2][q], iq = ec[3][q];
-                cc = readlane_d(cc, ol);
-                // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
-                const double num = r - cc + g * h;
-                double nw;
-                if (reg == VEST_REG_LF) {
-                    nw = num * iq;
-                } else {
-                    const double gg = -2.0 * num;
-                    nw = gg > lambda ? (lambda - gg) * iq : (gg < -lambda ? -(lambda + gg) * iq : 0.0);
-                }
-                const double dq = nw - g;
-                if (lane == ol) {
-                    eo[0][q] = nw;
-                    eo[1][q] = dq;
-                }
+            const bool dead = (mb >> ol) & 1ull;
+            const double g = readlane_d(vg, ol), r = readlane_d(vr, ol), h = readlane_d(vh, ol),
+                         iq = readlane_d(vi, ol);
+            const double cc = readlane_d(vc, ol);
+            // num_q = rr_q - sum_{p<q} H_qp D_p + G_q H_qq
+            const double num = r - cc + g * h;
+            double nw;
+            if constexpr (REG == VEST_REG_LF) {
+                nw = num * iq;
+            } else {
+                const double gg = -2.0 * num;
+                const double up = (lambda - gg) * iq, dn = -(lambda + gg) * iq;
+                nw = gg > lambda ? up : (gg < -lambda ? dn : 0.0);
+            }
+            nw = dead ? g : nw;
+            const double dq = nw - g;
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const int q2 = lane + c * kWave;
-                    corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hcur[c], dq, corr[c]) : corr[c];
-                }
+            for (int c = 0; c < CPL; ++c) {
+                const bool own = c == oc && lane == ol;
+                nwv[c] = own ? nw : nwv[c];
+                dqv[c] = own ? dq : dqv[c];
+                const int q2 = lane + c * kWave;
+                corr[c] = (q2 > q && q2 < B) ? __builtin_fma(hcur[c], dq, corr[c]) : corr[c];
             }
 #pragma unroll
             for (int c = 0; c < CPL; ++c) hcur[c] = hnxt[c];
@@ -957,23 +960,22 @@ __device__ __forceinline__ void slabsolve_body(const double *__restrict__ gram, 
 #pragma unroll
         for (int c = 0; c < CPL; ++c) ra[c] = rn[c];
     }
-    __syncthreads();
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
         const int q = lane + c * kWave;
         if (q < B) {
-            core[base + q] = eo[0][q];
-            dprev[q] = eo[1][q];
+            core[base + q] = nwv[c];
+            dprev[q] = dqv[c];
         }
     }
 }
 
-template <int J>
+template <int J, int REG>
 __global__ void __launch_bounds__(64) k_slabsolve(const double *__restrict__ gram, double *__restrict__ core,
                                                   const uint8_t *__restrict__ cmask, int64_t base, double lambda,
-                                                  int reg, double *__restrict__ dprev, double *__restrict__ hdiag)
+                                                  double *__restrict__ dprev, double *__restrict__ hdiag)
 {
-    slabsolve_body<J>(gram, core, cmask, base, lambda, reg, dprev, hdiag);
+    slabsolve_body<J, REG>(gram, core, cmask, base, lambda, dprev, hdiag);
 }
 
 struct SolveTask {
@@ -993,7 +995,10 @@ __global__ void __launch_bounds__(64) k_slabsolve_multi(const SolveTask *__restr
 {
     for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
         const SolveTask tk = tab[t];
-        slabsolve_body<J>(tk.gram, tk.core, tk.cmask, tk.base, tk.lambda, tk.reg, tk.dprev, tk.hdiag);
+        if (tk.reg == VEST_REG_LF)
+            slabsolve_body<J, VEST_REG_LF>(tk.gram, tk.core, tk.cmask, tk.base, tk.lambda, tk.dprev, tk.hdiag);
+        else
+            slabsolve_body<J, VEST_REG_L1>(tk.gram, tk.core, tk.cmask, tk.base, tk.lambda, tk.dprev, tk.hdiag);
         __syncthreads();   // LDS of the solve is reused by the next context
     }
 }
@@ -1003,26 +1008,28 @@ __global__ void __launch_bounds__(64) k_slabsolve_multi(const SolveTask *__restr
 // rr and H that slab's right-hand side and Gram matrix:
 //   sum (e - sum_q D_q w_q)^2 = sum e^2 - 2 D . rr + D^T H D,
 // sum e^2 being the per-wave sums of the last slab pass.  Fixed summation
-// order (one block).
-__device__ __forceinline__ void sse_lag_body(const double *__restrict__ wsum, int nwaves, int J, int GW,
+// order (one block of 1024 threads: its inputs were just written from every
+// XCD, so the block keeps many loads in flight).
+template <int J>
+__device__ __forceinline__ void sse_lag_body(const double *__restrict__ wsum, int nwaves,
                                              const double *__restrict__ gram, const double *__restrict__ dprev,
                                              double *__restrict__ out)
 {
-    __shared__ double sh[256];
-    const int B = J * J;
+    constexpr int GW = gram_width(J), B = J * J;
+    __shared__ double sh[1024];
     double s = 0.0;
+#pragma unroll 8
     for (int w = threadIdx.x; w < nwaves; w += blockDim.x) s += wsum[w];
+    // D^T H D over all element pairs, then - 2 D . rr
     double qf = 0.0;
-    for (int q = threadIdx.x; q < B; q += blockDim.x) {
-        const double dq = dprev[q];
-        if (dq != 0.0) {
-            const int t = q / J, u = q % J;
-            double hd = 0.0;
-            for (int p = 0; p < B; ++p)
-                hd += gram[(J + symr(J, t, p / J)) * GW + J + symr(J, u, p % J)] * dprev[p];
-            qf += dq * (hd - 2.0 * gram[t * GW + u]);
-        }
+#pragma unroll 8
+    for (int k = threadIdx.x; k < B * B; k += blockDim.x) {
+        const int q = k / B, p = k % B;
+        const double dq = dprev[q], dp = dprev[p];
+        if (dq != 0.0 && dp != 0.0)
+            qf += dq * dp * gram[(J + symr(J, q / J, p / J)) * GW + J + symr(J, q % J, p % J)];
     }
+    for (int q = threadIdx.x; q < B; q += blockDim.x) qf -= 2.0 * dprev[q] * gram[(q / J) * GW + q % J];
     const double S = block_sum(s, sh);
     __syncthreads();
     const double Q = block_sum(qf, sh);
@@ -1030,11 +1037,11 @@ __device__ __forceinline__ void sse_lag_body(const double *__restrict__ wsum, in
 }
 
 template <int J>
-__global__ void __launch_bounds__(256) k_sse_lag(const double *__restrict__ wsum, int nwaves,
+__global__ void __launch_bounds__(1024) k_sse_lag(const double *__restrict__ wsum, int nwaves,
                                                  const double *__restrict__ gram, const double *__restrict__ dprev,
                                                  double *__restrict__ out)
 {
-    sse_lag_body(wsum, nwaves, J, gram_width(J), gram, dprev, out);
+    sse_lag_body<J>(wsum, nwaves, gram, dprev, out);
 }
 
 struct SseTask {
@@ -1046,11 +1053,11 @@ struct SseTask {
 };
 
 template <int J>
-__global__ void __launch_bounds__(256) k_sse_lag_multi(const SseTask *__restrict__ tab, int ntask)
+__global__ void __launch_bounds__(1024) k_sse_lag_multi(const SseTask *__restrict__ tab, int ntask)
 {
     for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
         const SseTask tk = tab[t];
-        sse_lag_body(tk.wsum, tk.nwaves, J, gram_width(J), tk.gram, tk.dprev, tk.out);
+        sse_lag_body<J>(tk.wsum, tk.nwaves, tk.gram, tk.dprev, tk.out);
         __syncthreads();
     }
 }
@@ -1191,12 +1198,17 @@ static hipError_t core_pass_t(vest_ctx *c, bool keys, double *key_out, bool slab
         hipLaunchKernelGGL(k_gramsum_core<J>, dim3((gram_core_cells(J) + 63) / 64), dim3(1024), 0, st, c->gram_part,
                            gchunks, c->gram);
         const int64_t base = (int64_t)s * J * J;
-        hipLaunchKernelGGL(k_slabsolve<J>, dim3(1), dim3(64), 0, st, c->gram, c->core, c->cmask, base, c->d.lambda,
-                           c->d.reg, c->dprev, c->hdiag);
+        if (c->d.reg == VEST_REG_LF)
+            hipLaunchKernelGGL((k_slabsolve<J, VEST_REG_LF>), dim3(1), dim3(64), 0, st, c->gram, c->core, c->cmask,
+                               base, c->d.lambda, c->dprev, c->hdiag);
+        else
+            hipLaunchKernelGGL((k_slabsolve<J, VEST_REG_L1>), dim3(1), dim3(64), 0, st, c->gram, c->core, c->cmask,
+                               base, c->d.lambda, c->dprev, c->hdiag);
     }
     if (lag) {
         // the residual keeps lagging the last slab's change; its SSE is formed here
-        hipLaunchKernelGGL(k_sse_lag<J>, dim3(1), dim3(256), 0, st, c->wsum, L.nwaves, c->gram, c->dprev, c->sse_lag);
+        hipLaunchKernelGGL(k_sse_lag<J>, dim3(1), dim3(1024), 0, st, c->wsum, L.nwaves, c->gram, c->dprev,
+                           c->sse_lag);
         c->e_lag = true;
         return hipGetLastError();
     }
@@ -1367,7 +1379,7 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
             hipLaunchKernelGGL(k_slabsolve_multi<J>, dim3(grid(n)), dim3(64), 0, st, B.dptr<SolveTask>(o_solve[s]), n);
         }
         if (lag)
-            hipLaunchKernelGGL(k_sse_lag_multi<J>, dim3(grid(n)), dim3(256), 0, st, B.dptr<SseTask>(o_sse), n);
+            hipLaunchKernelGGL(k_sse_lag_multi<J>, dim3(grid(n)), dim3(1024), 0, st, B.dptr<SseTask>(o_sse), n);
         else if (tslab > 0)
             hipLaunchKernelGGL((k_slab_multi<N, J, T, false>), dim3(grid(tslab)), dim3(256), 0, st,
                                B.dptr<SlabArgs<N, J, T>>(o_final), B.dptr<int32_t>(o_soff), n, tslab);
