@@ -367,7 +367,7 @@ def sparse_phase(p, frac, steps, precision):
 
 def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
     """Serving stream: a pool of observed tensors and n_jobs jobs over it
-    (synth.serving_jobs); a serial pass of the first `calib` jobs (one slot,
+    (synth.serving_jobs, half of them pruning with VeST^man); a serial pass of the first `calib` jobs (one slot,
     all submitted at once) gives the serial rate; then the jobs arrive as a
     Poisson stream at 0.8 x that rate and run through one server with `slots`
     slots and an arena of arena_bytes.  Latency = completion - arrival, both
@@ -386,7 +386,8 @@ def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
         t = tensors[j["tensor"]]
         fac, core = synth.serving_init(j, t["dims"])
         return srv.submit(t["idx"], t["val"], fac, core, reg=j["reg"], lam=j["lam"],
-                          precision=getattr(vest, j["form"]), iterations=j["iterations"])
+                          precision=getattr(vest, j["form"]), iterations=j["iterations"],
+                          prune_target=j["prune_target"])
 
     def run(srv, arrivals):
         start = time.perf_counter()
@@ -437,6 +438,7 @@ def serving_bench(n_jobs, pool, arena_bytes, slots, calib):
             "pool_entries": int(sum(t["idx"].shape[0] for t in tensors)),
             "job_entries_total": int(sum(tensors[j["tensor"]]["idx"].shape[0] for j in jobs)),
             "forms": forms, "orders": {str(o): sum(1 for j in jobs if len(j["ranks"]) == o) for o in (3, 4)},
+            "pruning_jobs": sum(1 for j in jobs if j["prune_target"] > 0),
             "iterations_per_job": 10,
             "batched_iterations": {"poisson": st_p["batches"], "saturated": st_s["batches"]},
             "jobs_per_batch": {"poisson": st_p["batched_job_iterations"] / max(1, st_p["batches"]),

@@ -6,8 +6,8 @@
  * slots (one HIP stream each).  Jobs are queued on submission and admitted
  * in arrival order, later jobs filling in when the head of the queue does not
  * fit, as soon as a slot is free and the job's device footprint (observed
- * tensor, model state, marking tables and the vest_init workspace) fits in
- * the free part of the arena.  An admitted job keeps its state resident.
+ * tensor, model state, marking tables, the vest_init workspace and, for a
+ * pruning job, its keys) fits in the free part of the arena.  An admitted job keeps its state resident.
  * Admitted jobs of one class -- same order, rank and precision, entry counts
  * within a factor of 4 -- advance together:
  * the loop enqueues one batched iteration of Alg. 2 (every factor sweep,
@@ -48,8 +48,20 @@ typedef struct {
     const double *const *factors;   /* host array of N host arrays, I_n*J_n FP64,
                                        initial factors                            */
     const double *core;             /* host, prod(J_n) FP64, initial core         */
-    int32_t iterations;             /* iterations of Alg. 2 (>= 1), no pruning    */
+    int32_t iterations;             /* iterations of Alg. 2 (>= 1)                */
     int32_t reserved;               /* must be 0                                  */
+    double prune_target;            /* 0: no pruning.  In (0, 1): VeST^man toward
+                                       this sparsity (Sec. 3.3): after each
+                                       iteration t but the last, while the marked
+                                       fraction of all elements is below it,
+                                       responsibility keys and one prune step of
+                                       ceil(pr_t |T|) new marks per tensor,
+                                       pr_t = min(0.01 t, 0.1), each tensor capped
+                                       at ceil(target |T|) marks.  Equal ranks
+                                       only; such a job iterates alone on its
+                                       slot's stream and reserves its keys
+                                       (prod J_n + sum I_n J_n doubles) in the
+                                       arena.                                      */
 } vest_job;
 
 /* One iteration of Alg. 2 (the factor sweep of every mode, Alg. 4, then the
@@ -79,8 +91,9 @@ int vest_iterate_many(vest_ctx *const *ctxs, int32_t n, void *stream, void *dev_
 int vest_server_create(size_t device_bytes, int32_t slots, vest_server **out /* host out */);
 
 /* Queue a job; its arrival time is the time of this call.  VEST_ENOSPC if its
- * footprint exceeds the whole arena, VEST_EINVAL for a bad descriptor or
- * iteration count (checked as vest_init does, without touching the data). */
+ * footprint exceeds the whole arena, VEST_EINVAL for a bad descriptor,
+ * iteration count or prune target (checked as vest_init does, without
+ * touching the data). */
 int vest_server_submit(vest_server *s, const vest_job *job, int64_t *id /* host out */);
 
 /* One scheduling pass: retire jobs whose last iteration has completed, make

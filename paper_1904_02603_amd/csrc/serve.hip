@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -108,12 +109,15 @@ struct Job {
     double t_arrive = -1, t_admit = -1, t_done = -1;
     size_t ws_bytes = 0;
     // device blocks: 0 workspace, 1 factors, 2 core, 3 factor masks, 4 core
-    // mask, 5 idx, 6 val (5 and 6 only until vest_init has returned)
-    Block blk[7];
+    // mask, 5 idx, 6 val (5 and 6 only until vest_init has returned), 7 the
+    // responsibility keys of a pruning job (core, then each factor matrix)
+    static constexpr int kBlocks = 8;
+    Block blk[kBlocks];
     vest_ctx *ctx = nullptr;
     int slot = -1;
     int klass = -1;          // shape class (batched iterations), -1 until admitted
     int32_t iters_done = 0;
+    int32_t prune_steps = 0;
     // admission on the worker thread: init_rc is valid once init_done is set
     std::atomic<int> init_done{0};
     int init_rc = 0;
@@ -145,13 +149,15 @@ struct Job {
         case 3: return mask_words() * 4;
         case 4: return (size_t)G;
         case 5: return (size_t)in.desc.nnz * N * 4;
-        default: return (size_t)in.desc.nnz * 8;
+        case 6: return (size_t)in.desc.nnz * 8;
+        default: return in.prune_target > 0.0 ? ((size_t)G + fac_elems()) * 8 : 0;
         }
     }
     size_t footprint() const
     {
         size_t s = 0;
-        for (int b = 0; b < 7; ++b) s += align_up(block_bytes(b));
+        for (int b = 0; b < kBlocks; ++b)
+            if (block_bytes(b)) s += align_up(block_bytes(b));
         return s;
     }
 };
@@ -250,8 +256,9 @@ JobPtrs job_ptrs(vest_server *s, Job &j)
 // hold it now.  Progress thread.
 bool alloc_blocks(vest_server *s, Job &j)
 {
-    for (int b = 0; b < 7; ++b) {
+    for (int b = 0; b < Job::kBlocks; ++b) {
         j.blk[b].bytes = j.block_bytes(b);
+        if (!j.blk[b].bytes) continue;
         if (!s->arena.alloc(j.blk[b].bytes, &j.blk[b].off)) {
             release_blocks(s, j);
             return false;
@@ -359,9 +366,50 @@ int klass_of(vest_server *s, const Job &j)
     return (int)s->classes.size() - 1;
 }
 
+// VeST^man of a pruning job (Sec. 3.3, the schedule of paper_1904_02603_amd
+// /schedule.py): after iteration t (t < iterations) and while the marked
+// fraction of all elements is below the target, one prune step of
+// ceil(pr_t |T|) new marks per tensor, pr_t = min(0.01 t, 0.1), each tensor
+// capped at ceil(target |T|) marks; keys from vest_responsibility.
+int64_t prune_count(int t, int64_t size, int64_t marked, double target)
+{
+    const double pr = std::min(0.01 * t, 0.1);
+    const int64_t want = (int64_t)std::ceil(pr * (double)size - 1e-12);
+    const int64_t room = std::min(size - marked, (int64_t)std::ceil(target * (double)size - 1e-12) - marked);
+    return std::max<int64_t>(0, std::min(want, room));
+}
+
+int prune_step(vest_server *s, Job &j)
+{
+    const int t = j.iters_done;
+    if (!(j.in.prune_target > 0.0) || t < 1 || t >= j.in.iterations) return VEST_OK;
+    vest_ctx *c = j.ctx;
+    int64_t marked = c->marked_core, total = j.G;
+    for (int n = 0; n < j.N; ++n) {
+        marked += c->marked_fac[n];
+        total += (int64_t)j.in.desc.dims[n] * j.in.desc.ranks[n];
+    }
+    if ((double)marked >= j.in.prune_target * (double)total) return VEST_OK;
+    double *keys = (double *)s->ptr(j.blk[7]);
+    double *fk[VEST_MAX_ORDER];
+    int64_t kf[VEST_MAX_ORDER];
+    double *q = keys + j.G;
+    for (int n = 0; n < j.N; ++n) {
+        const int64_t sz = (int64_t)j.in.desc.dims[n] * j.in.desc.ranks[n];
+        fk[n] = q;
+        q += sz;
+        kf[n] = prune_count(t, sz, c->marked_fac[n], j.in.prune_target);
+    }
+    const int64_t kc = prune_count(t, j.G, c->marked_core, j.in.prune_target);
+    int rc = vest_responsibility(c, keys, fk);
+    if (rc == VEST_OK) rc = vest_prune(c, kc, kf);
+    if (rc == VEST_OK) j.prune_steps++;
+    return rc;
+}
+
 int enqueue_iteration(vest_server *s, Job &j)
 {
-    int rc = VEST_OK;
+    int rc = prune_step(s, j);   // the prune step that follows the previous iteration
     for (int n = 0; n < j.N && rc == VEST_OK; ++n) rc = vest_sweep_factor(j.ctx, n);
     if (rc == VEST_OK) rc = vest_sweep_core(j.ctx);
     if (rc != VEST_OK) return rc;
@@ -383,6 +431,10 @@ std::vector<int64_t> enqueue_class(vest_server *s, int k)
     for (int64_t id : s->active) {
         Job &j = *s->jobs[id];
         if (j.klass == k && !j.inflight && j.iters_done < j.in.iterations) {
+            if (j.in.prune_target > 0.0) {   // pruning jobs run alone on their slot stream
+                if (enqueue_iteration(s, j) != VEST_OK) failed.push_back(id);
+                continue;
+            }
             ids.push_back(id);
             cs.push_back(j.ctx);
         }
@@ -493,6 +545,13 @@ int vest_server_submit(vest_server *s, const vest_job *job, int64_t *id)
     int rc = vest::check_desc(&job->desc);
     if (rc) return rc;
     if (job->iterations < 1 || job->reserved != 0) { set_error("iterations must be >= 1, reserved 0"); return VEST_EINVAL; }
+    if (!(job->prune_target >= 0.0 && job->prune_target < 1.0)) { set_error("prune_target outside [0, 1)"); return VEST_EINVAL; }
+    if (job->prune_target > 0.0)
+        for (int n = 1; n < job->desc.order; ++n)
+            if (job->desc.ranks[n] != job->desc.ranks[0]) {
+                set_error("a pruning job needs equal ranks");
+                return VEST_EINVAL;
+            }
     if (!job->idx || !job->val || !job->factors || !job->core) { set_error("null job array"); return VEST_EINVAL; }
     for (int n = 0; n < job->desc.order; ++n)
         if (!job->factors[n]) { set_error("null factor %d", n); return VEST_EINVAL; }

@@ -225,8 +225,11 @@ def serving_jobs(n_jobs, tensors, seed=SEED_BASE + 6):
     probability, 10 iterations, and a seed for its U[0, 1) initial state
     (serving_init).  The BF16 form differs from the FP32 form only in the
     order-3 factor sweep (matrix cores), so an order-4 job that draws BF16 is
-    labelled and run as FP32."""
+    labelled and run as FP32.  Every job prunes with probability 1/2 (VeST^man
+    toward 0.95, Sec. 3.3; the flag comes from a generator of its own, so the
+    rest of the stream is unchanged by it)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    rng_p = np.random.Generator(np.random.PCG64(seed + 1))
     jobs = []
     for i in range(n_jobs):
         k = int(rng.integers(0, len(tensors)))
@@ -235,7 +238,7 @@ def serving_jobs(n_jobs, tensors, seed=SEED_BASE + 6):
         reg = int(rng.integers(0, 2))
         jobs.append({"tensor": k, "ranks": (J,) * N, "reg": reg, "lam": 0.01 if reg == 0 else 0.1,
                      "form": "FP32" if (rng.random() < 0.5 or N != 3) else "BF16", "iterations": 10,
-                     "init_seed": (seed, i)})
+                     "init_seed": (seed, i), "prune_target": 0.95 if rng_p.random() < 0.5 else 0.0})
     return jobs
 
 

@@ -353,21 +353,23 @@ def model_error_noalloc(factors, core, idx, val, out, stream=None):
            "vest_model_error_noalloc")
 
 
-def job_footprint(dims, ranks, nnz, reg=REG_LF, lam=0.01, precision=FP32):
+def job_footprint(dims, ranks, nnz, reg=REG_LF, lam=0.01, precision=FP32, prune_target=0.0):
     """Device bytes a server reserves to admit a job (see vest_serve.h)."""
     def a(x):
         return (int(x) + 255) // 256 * 256
     N = len(dims)
     G = int(np.prod(ranks))
     ws = workspace_bytes(dims, ranks, nnz, reg, lam, precision)
-    return (a(ws) + a(sum(I * J for I, J in zip(dims, ranks)) * 8) + a(G * 8) + a(sum(dims) * 4) + a(G)
-            + a(nnz * N * 4) + a(nnz * 8))
+    fac = sum(I * J for I, J in zip(dims, ranks))
+    keys = a((G + fac) * 8) if prune_target > 0 else 0
+    return (a(ws) + a(fac * 8) + a(G * 8) + a(sum(dims) * 4) + a(G) + a(nnz * N * 4) + a(nnz * 8) + keys)
 
 
 class Job(C.Structure):
     """vest_job of vest_serve.h."""
     _fields_ = [("desc", Desc), ("idx", C.c_void_p), ("val", C.c_void_p), ("factors", C.c_void_p),
-                ("core", C.c_void_p), ("iterations", C.c_int32), ("reserved", C.c_int32)]
+                ("core", C.c_void_p), ("iterations", C.c_int32), ("reserved", C.c_int32),
+                ("prune_target", C.c_double)]
 
 
 class VestServer:
@@ -381,8 +383,10 @@ class VestServer:
         self._keep = {}
         self._shape = {}
 
-    def submit(self, idx, val, factors, core, reg=REG_LF, lam=0.01, precision=FP32, iterations=10):
-        """Queue a job (numpy host arrays); returns its id."""
+    def submit(self, idx, val, factors, core, reg=REG_LF, lam=0.01, precision=FP32, iterations=10,
+               prune_target=0.0):
+        """Queue a job (numpy host arrays); returns its id.  prune_target > 0
+        runs VeST^man toward that sparsity (see vest_job in vest_serve.h)."""
         idx = np.ascontiguousarray(idx, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float64)
         factors = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
@@ -395,6 +399,7 @@ class VestServer:
         j.idx, j.val, j.factors, j.core = idx.ctypes.data, val.ctypes.data, C.cast(fp, C.c_void_p), core.ctypes.data
         j.iterations = int(iterations)
         j.reserved = 0
+        j.prune_target = float(prune_target)
         jid = C.c_int64(0)
         _check(self.lib.vest_server_submit(self.srv, C.byref(j), C.byref(jid)), "vest_server_submit")
         self._keep[jid.value] = (idx, val, factors, core, fp, j)

@@ -7,8 +7,10 @@ each result must equal bit for bit the same job run alone through the plain
 context (every kernel sums in a fixed order and the batched kernels run the
 same per-job arithmetic, so the mix cannot change a result).  Served results
 are checked against the oracle (FP64 at the FP64 bar, FP32 / split-BF16
-within 1e-4 relative RE and factor RMSE).  The arena bound, the rejection of
-a job larger than the arena and the failure of a job with invalid data are
+within 1e-4 relative RE and factor RMSE).  Jobs with a VeST^man prune target
+(Sec. 3.3) end where the same schedule on a plain context ends, bit for bit,
+and an FP64 one where the oracle ends.  The arena bound, the rejection of a
+job larger than the arena and the failure of a job with invalid data are
 checked as well.
 """
 import time
@@ -160,4 +162,117 @@ def test_served_jobs_match_oracle():
             assert rel_err(core, o.core) <= 1e-10
         else:
             assert gap <= 1e-4 and fr <= 1e-4
+    srv.close()
+
+
+PRUNE_JOBS = [
+    # job index in JOBS, iterations, prune target (VeST^man)
+    (0, 8, 0.6),     # FP32, order 3
+    (2, 6, 0.5),     # FP32, order 4
+    (1, 10, 0.9),    # split-BF16, rank 10, L_1
+    (5, 6, 0.7),     # FP64, order 4
+]
+
+
+def pruned_alone(p, reg, lam, prec, iters, target):
+    """The server's VeST^man on a plain context: iteration t, then (t below
+    the last iteration, marked fraction below the target) keys and one prune
+    step with the counts of the host schedule."""
+    from paper_1904_02603_amd.schedule import PruneSchedule
+    v = V()
+    sched = PruneSchedule(mode="manual", target=target)
+    ctx = v.VestContext(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec)
+    total = ctx.core.numel() + sum(f.numel() for f in ctx.factors)
+    steps = 0
+    for t in range(1, iters + 1):
+        ctx.iteration()
+        if t < iters:
+            fm, cm = ctx.marked_counts()
+            if cm + sum(fm) < target * total:
+                ctx.responsibility()
+                ctx.prune(sched.count(t, ctx.core.numel(), cm),
+                          [sched.count(t, f.numel(), m) for f, m in zip(ctx.factors, fm)])
+                steps += 1
+    L = ctx.loss()
+    torch.cuda.synchronize()
+    out = ([f.cpu().numpy().copy() for f in ctx.factors], ctx.core.cpu().numpy().copy(), L, steps)
+    ctx.close()
+    return out
+
+
+def test_served_pruning_equals_plain_context():
+    """Jobs with a VeST^man target, mixed with plain jobs in one server, end
+    bit for bit where the same schedule run on a plain context ends."""
+    v = V()
+    srv = v.VestServer(1 << 30, 3)
+    ins = [job_inputs(k) for k, _, _ in PRUNE_JOBS]
+    ids = [srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec,
+                      iterations=it, prune_target=tg)
+           for (p, reg, lam, prec), (_, it, tg) in zip(ins, PRUNE_JOBS)]
+    plain = [job_inputs(k) for k in (3, 4)]
+    ids += [srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec, iterations=3)
+            for p, reg, lam, prec in plain]
+    drain(srv, ids)
+    for jid, (p, reg, lam, prec), (k, it, tg) in zip(ids, ins, PRUNE_JOBS):
+        assert srv.status(jid)["state"] == v.JOB_DONE, (k, srv.status(jid))
+        fac, core, loss = srv.fetch(jid)
+        afac, acore, aloss, steps = pruned_alone(p, reg, lam, prec, it, tg)
+        zeros = (sum(int((f == 0).sum()) for f in fac) + int((core == 0).sum())) / (
+            sum(f.size for f in fac) + core.size)
+        say("job %d: %d prune steps, zeros %.3f, RE %.6f" % (k, steps, zeros, loss["re"]))
+        assert steps >= 2
+        for n in range(len(fac)):
+            assert np.array_equal(fac[n], afac[n]), (k, n)
+        assert np.array_equal(core, acore), k
+        assert loss["loss"] == aloss["loss"] and loss["re"] == aloss["re"], k
+    for jid in ids[len(PRUNE_JOBS):]:
+        assert srv.status(jid)["state"] == v.JOB_DONE
+    srv.close()
+
+
+def test_served_fp64_pruning_matches_oracle():
+    from oracle.oracle import Oracle
+    from paper_1904_02603_amd.schedule import PruneSchedule
+    from test_gpu_parity import rel_err
+    v = V()
+    p, reg, lam, prec = job_inputs(5)    # FP64, order 4
+    iters, target = 6, 0.7
+    srv = v.VestServer(1 << 30, 2)
+    jid = srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec,
+                     iterations=iters, prune_target=target)
+    drain(srv, [jid])
+    fac, core, loss = srv.fetch(jid)
+    srv.close()
+    o = Oracle(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam)
+    sched = PruneSchedule(mode="manual", target=target)
+    total = o.core.size + sum(f.size for f in o.factors)
+    for t in range(1, iters + 1):
+        o.iteration()
+        marked = int(o.cmask.sum()) + sum(int(m.sum()) for m in o.fmask)
+        if t < iters and marked < target * total:
+            ck, fk = o.responsibility()
+            o.prune(ck, fk, sched.count(t, o.core.size, int(o.cmask.sum())),
+                    [sched.count(t, f.size, int(m.sum())) for f, m in zip(o.factors, o.fmask)])
+    for f, of in zip(fac, o.factors):
+        assert np.array_equal(f == 0, of == 0)
+        assert rel_err(f, of) <= 1e-10
+    assert np.array_equal(core == 0, o.core == 0)
+    assert rel_err(core, o.core) <= 1e-10
+    ol = o.loss()
+    assert abs(loss["re"] - ol["re"]) <= 1e-10 * ol["re"]
+
+
+def test_pruning_job_arguments():
+    v = V()
+    p, reg, lam, prec = job_inputs(0)
+    srv = v.VestServer(1 << 28, 2)
+    for bad in (-0.1, 1.0):
+        with pytest.raises(v.VestError) as ei:
+            srv.submit(p["idx"], p["val"], p["factors"], p["core"], reg=reg, lam=lam, precision=prec,
+                       prune_target=bad)
+        assert ei.value.code == v.EINVAL
+    q = synth.make_problem((50, 40, 30), 3000, (4, 3, 5), 7, noise_var=0.01)
+    with pytest.raises(v.VestError) as ei:   # unequal ranks
+        srv.submit(q["idx"], q["val"], q["factors"], q["core"], prune_target=0.5)
+    assert ei.value.code == v.EINVAL
     srv.close()
