@@ -274,6 +274,20 @@ static int ensure_residual(vest_ctx *c)
     return VEST_OK;
 }
 
+// Live partition of the layouts once marks have changed (before a factor
+// sweep or the factor keys read klive).  It moves entries of the core layout,
+// so the residual and its slot copy must be formed again.
+static int ensure_live(vest_ctx *c, hipStream_t st)
+{
+    if (!c->live_stale) return VEST_OK;
+    CALL_HIP(c, launch_live_partition(c, st), "live partition");
+    c->live_stale = false;
+    c->e_valid = false;
+    c->ms_valid = false;
+    c->e_lag = false;
+    return VEST_OK;
+}
+
 static int live(vest_ctx *c)
 {
     if (!c) { set_error("null context"); return VEST_EINVAL; }
@@ -414,6 +428,7 @@ int vest_sweep_factor(vest_ctx *c, int32_t mode)
     int rc = live(c);
     if (rc) return rc;
     if (mode < 0 || mode >= c->N) { set_error("mode %d outside 0..%d", mode, c->N - 1); return VEST_EINVAL; }
+    if ((rc = ensure_live(c, c->stream))) return rc;
     if ((rc = ensure_ag(c))) return rc;
     if ((rc = ensure_gp(c, mode))) return rc;
     CALL_HIP(c, launch_rowgroup(c, mode, OP_SWEEP), "factor sweep");
@@ -470,6 +485,10 @@ int vest_iterate_many(vest_ctx *const *cs, int32_t n, void *stream, void *dev_ta
         }
     }
     hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        int rc = ensure_live(cs[i], st);
+        if (rc) return rc;
+    }
     BatchArena ba;
     ba.host = (char *)host_table;
     ba.dev = (char *)dev_table;
@@ -512,6 +531,7 @@ int vest_responsibility(vest_ctx *c, double *core_key, double *const *factor_key
     if (!core_key || !factor_key) { set_error("null key pointer"); return VEST_EINVAL; }
     for (int n = 0; n < c->N; ++n)
         if (!factor_key[n]) { set_error("null factor key pointer (mode %d)", n); return VEST_EINVAL; }
+    if ((rc = ensure_live(c, c->stream))) return rc;
     if ((rc = ensure_residual(c))) return rc;
     for (int n = 0; n < c->N; ++n)
         if ((rc = ensure_gp(c, n))) return rc;
@@ -579,6 +599,7 @@ int vest_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k)
             c->ag_valid[n] = false;
             c->ms_valid = false;
             c->hdiag_valid = false;
+            c->live_stale = true;
         }
     c->e_valid = false;
     c->keys_pending = false;
@@ -632,6 +653,7 @@ int vest_compact(vest_ctx *c, int64_t *live_out)
     c->e_valid = false;
     c->ms_valid = false;
     c->hdiag_valid = false;
+    c->live_stale = true;   // the rebuilt layouts start with every step live
     return VEST_OK;
 }
 

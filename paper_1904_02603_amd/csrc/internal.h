@@ -57,6 +57,7 @@ constexpr int kLaneTargetSmall = 8, kLaneTargetLarge = 16;
 constexpr int64_t kLaneTargetLargeFrom = int64_t(1) << 22;
 inline int lane_target_for(int64_t nnz) { return nnz >= kLaneTargetLargeFrom ? kLaneTargetLarge : kLaneTargetSmall; }
 constexpr int kGramRows = 128;                    // rows per gram partial
+constexpr int kGatherGrid = 1024;                 // blocks of a gather-form pass (core staged once per block)
 constexpr int kLossBlocks = 1024;                 // fixed grid of the loss reductions
 constexpr int64_t kSideStreamMinNnz = 1 << 20;    // entries from which the key passes overlap
 
@@ -67,7 +68,7 @@ struct WaveInfo {
     int32_t first;  // position in row_order of the wave's first row
     int32_t nrows;  // rows in this wave
     int32_t chunk;  // long-row chunk id (partial slot) or -1
-    int32_t pad_;
+    int32_t klive;  // steps that hold live entries (<= K; see launch_live_partition)
 };
 static_assert(sizeof(WaveInfo) == 32, "WaveInfo layout");
 
@@ -246,6 +247,7 @@ struct vest_ctx {
     uint64_t gp_version[VEST_MAX_ORDER] = {};
     bool ag_valid[VEST_MAX_ORDER] = {};
     bool e_valid = false;
+    bool live_stale = true;           // marks changed since the layouts' live partition
     // e lacks the change of the core sweep's last slab (held in dprev); the
     // SSE it would have is in sse_lag, and the change is applied to e only
     // when something reads e
@@ -287,6 +289,11 @@ hipError_t launch_permute_core(vest_ctx *c, int mode);
 hipError_t launch_gather_copy(vest_ctx *c, int mode);
 hipError_t launch_loss(vest_ctx *c, double *dev_out3, const double *sse);   // sse, reg (device); sse given or summed over e
 hipError_t launch_lag_apply(vest_ctx *c);   // apply the core sweep's last slab change to e
+// Live partition of every mode's layout after marks changed: each lane's
+// entries with no fully marked other-mode row (those whose delta can be
+// nonzero) move ahead of the others, in order, and every wave records in
+// klive the steps that hold them; factor sweeps and factor keys stop there.
+hipError_t launch_live_partition(vest_ctx *c, hipStream_t st);
 hipError_t launch_prune(vest_ctx *c, int64_t core_k, const int64_t *factor_k);  // all tensors at once
 hipError_t launch_sumsq(hipStream_t s, const double *v, int64_t n, double *partial, double *out);
 hipError_t launch_mask_init(vest_ctx *c, int64_t *counts_dev);

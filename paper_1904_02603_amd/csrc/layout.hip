@@ -196,6 +196,7 @@ static void plan_mode(const std::vector<uint32_t> &cnt, int lt, HostPlan &hp)
             w.first = (int32_t)hp.row_order.size();
             w.nrows = nrows;
             w.chunk = -1;
+            w.klive = K;
             for (int j = 0; j < nrows; ++j) {
                 hp.place[v[i + j]] = RowPlace{slot, c, j};
                 hp.row_order.push_back(v[i + j]);
@@ -220,6 +221,7 @@ static void plan_mode(const std::vector<uint32_t> &cnt, int lt, HostPlan &hp)
             w.first = pos;
             w.nrows = 1;
             w.chunk = hp.nchunks++;
+            w.klive = w.K;
             hp.waves.push_back(w);
             slot += (int64_t)kWave * w.K;
         }
@@ -474,6 +476,105 @@ hipError_t launch_compact(vest_ctx *c, int32_t **idx_out, double **val_out, int6
     *idx_out = idx;
     *val_out = val;
     return hipSuccess;
+}
+
+// Live partition (see internal.h).  One wave per layout wave; lane l reads
+// its K <= 16 slots (indices, value, canonical id), marks each live or dead
+// and writes them back live first, in order, then dead; klive of the wave is
+// the largest live count of its lanes.  Dead entries contribute exactly zero
+// to the factor sweeps and keys (delta = 0), so stopping at klive changes no
+// result.  Padding slots count as dead and already sit at the end.
+constexpr int kLiveMaxK = 16;
+
+template <int N, typename T>
+__global__ void __launch_bounds__(256) k_live_partition(WaveInfo *__restrict__ waves, int nwaves, OidxArg oidx,
+                                                        T *__restrict__ xval, int32_t *__restrict__ perm,
+                                                        MaskArg masks, uint32_t full)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= nwaves) return;
+    const WaveInfo wi = waves[w];
+    const int K = wi.K < kLiveMaxK ? wi.K : kLiveMaxK;
+    int32_t id[kLiveMaxK][N - 1], pv[kLiveMaxK];
+    T xv[kLiveMaxK];
+    bool live[kLiveMaxK];
+    int nlive = 0;
+#pragma unroll
+    for (int k = 0; k < kLiveMaxK; ++k) {
+        live[k] = false;
+        if (k < K) {
+            const int64_t sl = wi.base + (int64_t)k * kWave + lane;
+#pragma unroll
+            for (int m = 0; m < N - 1; ++m) id[k][m] = oidx.p[m][sl];
+            xv[k] = xval[sl];
+            pv[k] = perm[sl];
+            bool ok = id[k][0] >= 0;
+#pragma unroll
+            for (int m = 0; m < N - 1; ++m) ok = ok && ((~masks.p[m][ok ? id[k][m] : 0]) & full) != 0u;
+            live[k] = ok;
+            nlive += ok ? 1 : 0;
+        }
+    }
+    int nl = 0, nd = nlive;
+#pragma unroll
+    for (int k = 0; k < kLiveMaxK; ++k) {
+        if (k < K) {
+            const int dst = live[k] ? nl++ : nd++;
+            const int64_t sl = wi.base + (int64_t)dst * kWave + lane;
+#pragma unroll
+            for (int m = 0; m < N - 1; ++m) oidx.p[m][sl] = id[k][m];
+            xval[sl] = xv[k];
+            perm[sl] = pv[k];
+        }
+    }
+    int kl = nlive;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const int o = __shfl_xor(kl, d);
+        kl = o > kl ? o : kl;
+    }
+    if (lane == 0) waves[w].klive = kl;
+}
+
+template <int N>
+static hipError_t live_partition_n(vest_ctx *c, hipStream_t st)
+{
+    const uint32_t full = c->J >= 32 ? 0xffffffffu : (1u << c->J) - 1u;
+    for (int n = 0; n < N; ++n) {
+        ModeLayout &L = c->lay[n];
+        if (L.nwaves == 0) continue;
+        OidxArg oa{};
+        MaskArg ma{};
+        for (int m = 0; m < N - 1; ++m) {
+            oa.p[m] = L.oidx[m];
+            ma.p[m] = c->fmask[m < n ? m : m + 1];
+        }
+        const int blocks = (L.nwaves + 3) / 4;
+        if (c->f32)
+            hipLaunchKernelGGL((k_live_partition<N, float>), dim3(blocks), dim3(256), 0, st, L.waves, L.nwaves, oa,
+                               reinterpret_cast<float *>(L.xval), L.perm, ma, full);
+        else
+            hipLaunchKernelGGL((k_live_partition<N, double>), dim3(blocks), dim3(256), 0, st, L.waves, L.nwaves, oa,
+                               reinterpret_cast<double *>(L.xval), L.perm, ma, full);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_live_partition(vest_ctx *c, hipStream_t st)
+{
+    switch (c->N) {
+    case 2: return live_partition_n<2>(c, st);
+    case 3: return live_partition_n<3>(c, st);
+    case 4: return live_partition_n<4>(c, st);
+    case 5: return live_partition_n<5>(c, st);
+    case 6: return live_partition_n<6>(c, st);
+    case 7: return live_partition_n<7>(c, st);
+    case 8: return live_partition_n<8>(c, st);
+    case 9: return live_partition_n<9>(c, st);
+    case 10: return live_partition_n<10>(c, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace vest

@@ -225,7 +225,7 @@ template <int N, int J, typename T, int OP>
 __device__ __forceinline__ void pair_steps(const RowArgs<N, J, T> &a, const CoreBases<T> &Gb, const WaveInfo &wi,
                                            int lane, const T (&own)[J], T (&s)[row_nacc<J, OP>()])
 {
-    const int K = wi.K;
+    const int K = OP == OP_KEYS ? wi.klive : wi.K;   // keys: live entries only (the rest add zero)
     int32_t ia[N - 1], ib[N - 1];
     T xa = T(0), xb = T(0);
     auto load_pair = [&](int k, int32_t (&i0)[N - 1], T &x0, int32_t (&i1)[N - 1], T &x1) {
@@ -304,7 +304,7 @@ __device__ __forceinline__ void pair_steps(const RowArgs<N, J, T> &a, const Core
 // GA = false: dense factored contraction, core operands as scalar loads.
 // GA = true : pruned-phase gather contraction from LDS (dynamic LDS of
 //             gather_lds_bytes<N, J, T>() bytes).
-template <int N, int J, typename T, int OP, bool GA>
+template <int N, int J, typename T, int OP, bool GA, bool STAGE = true>
 __device__ __forceinline__ void rowgroup_body(const RowArgs<N, J, T> &a, const T *__restrict__ Gp, int bx,
                                               char *smem)
 {
@@ -312,9 +312,11 @@ __device__ __forceinline__ void rowgroup_body(const RowArgs<N, J, T> &a, const T
     const T *Gt = a.gt;
     const uint32_t *Gnz = a.gnz;
     if constexpr (GA && gather_in_lds(N, J, (int)sizeof(T))) {
+        // STAGE = false: the block staged the core already (k_rowgroup's
+        // grid-stride form of the gather contraction)
         T *g = reinterpret_cast<T *>(smem);
         uint32_t *nz = reinterpret_cast<uint32_t *>(smem + (size_t)ipow(J, N) * sizeof(T));
-        stage_core<N, J, T>(Gp, g, nz);
+        if constexpr (STAGE) stage_core<N, J, T>(Gp, g, nz);
         Gt = g;
         Gnz = nz;
     }
@@ -348,7 +350,9 @@ __device__ __forceinline__ void rowgroup_body(const RowArgs<N, J, T> &a, const T
     // Prefetches past the last step re-read that step (in range).
     constexpr uint32_t full = J == 32 ? 0xffffffffu : (1u << J) - 1u;
     constexpr int AHEAD = GA ? 2 : 1;
-    const int K = wi.K;
+    // the sweep and the keys stop after the live entries (the rest add zero);
+    // the residual passes write every slot
+    const int K = (OP == OP_SWEEP || OP == OP_KEYS) ? wi.klive : wi.K;
     int32_t ci[N - 1], pi[N - 1];
     uint32_t cm[N - 1];
     T cx = T(0), px = T(0);
@@ -484,7 +488,17 @@ template <int N, int J, typename T, int OP, bool GA>
 __global__ void __launch_bounds__(256) k_rowgroup(RowArgs<N, J, T> a, const T *__restrict__ Gp)
 {
     extern __shared__ __align__(16) char smem[];
-    rowgroup_body<N, J, T, OP, GA>(a, Gp, blockIdx.x, smem);
+    if constexpr (GA && gather_in_lds(N, J, (int)sizeof(T))) {
+        // gather form: the core is staged in LDS once per block, then the
+        // block walks its share of the waves (grid of at most kGatherGrid
+        // blocks), so the staging is not repeated for every four waves
+        stage_core<N, J, T>(Gp, reinterpret_cast<T *>(smem),
+                            reinterpret_cast<uint32_t *>(smem + (size_t)ipow(J, N) * sizeof(T)));
+        for (int bx = blockIdx.x; bx * (int)(blockDim.x / kWave) < a.nwaves; bx += gridDim.x)
+            rowgroup_body<N, J, T, OP, GA, false>(a, Gp, bx, smem);
+    } else {
+        rowgroup_body<N, J, T, OP, GA>(a, Gp, blockIdx.x, smem);
+    }
 }
 
 // Several contexts of one shape in one launch (dense contraction): block b of
@@ -634,7 +648,7 @@ __device__ __forceinline__ void rowgroup_mfma_body(const RowArgs<3, J, float> &a
 #pragma unroll
     for (int v = 0; v < NA; ++v) s[v] = 0.0f;
 
-    for (int k = 0; k < wi.K; ++k) {
+    for (int k = 0; k < wi.klive; ++k) {   // live entries only (the rest add zero)
         const int64_t sl = wi.base + (int64_t)k * kWave + lane;
         const int32_t i0 = ld_stream(a.oidx[0] + sl);
         const int32_t i1 = ld_stream(a.oidx[1] + sl);  // 0 on padding slots
@@ -831,12 +845,13 @@ static hipError_t launch_rowgroup_t(vest_ctx *c, int mode, int op)
         }
         if (done) {
         } else if (ga) {
+            const int gb = gather_in_lds(N, J, (int)sizeof(T)) && blocks > kGatherGrid ? kGatherGrid : blocks;
             if (op == OP_SWEEP)
-                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, true>), dim3(gb), dim3(256), lds, c->stream, a, Gp);
             else if (op == OP_KEYS)
-                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_KEYS, true>), dim3(gb), dim3(256), lds, c->stream, a, Gp);
             else
-                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, true>), dim3(blocks), dim3(256), lds, c->stream, a, Gp);
+                hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_RESID, true>), dim3(gb), dim3(256), lds, c->stream, a, Gp);
         } else if constexpr (dense_form(N, J)) {
             if (op == OP_SWEEP)
                 hipLaunchKernelGGL((k_rowgroup<N, J, T, OP_SWEEP, false>), dim3(blocks), dim3(256), 0, c->stream, a, Gp);
