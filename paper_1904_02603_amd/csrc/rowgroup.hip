@@ -350,9 +350,13 @@ __device__ __forceinline__ void rowgroup_body(const RowArgs<N, J, T> &a, const T
     // Prefetches past the last step re-read that step (in range).
     constexpr uint32_t full = J == 32 ? 0xffffffffu : (1u << J) - 1u;
     constexpr int AHEAD = GA ? 2 : 1;
-    // the sweep and the keys stop after the live entries (the rest add zero);
-    // the residual passes write every slot
-    const int K = (OP == OP_SWEEP || OP == OP_KEYS) ? wi.klive : wi.K;
+    // the gather-form sweep and the keys stop after the live entries (the
+    // rest add zero); the residual passes write every slot.  The dense FP64
+    // sweep at J = 10 sits at the 256-VGPR line of two waves per SIMD and the
+    // live bound tips its allocation over it (a few AGPRs, one wave per
+    // SIMD), so the dense sweep walks every slot: its dead entries, whose
+    // other-mode rows are zero, add exact zeros.
+    const int K = (OP == OP_KEYS || (OP == OP_SWEEP && GA)) ? wi.klive : wi.K;
     int32_t ci[N - 1], pi[N - 1];
     uint32_t cm[N - 1];
     T cx = T(0), px = T(0);
