@@ -695,17 +695,19 @@ __global__ void __launch_bounds__(64 * gram_tm(J)) k_gram_core(const double *__r
     gram_core_body<J>(rb, ldrb, kp, ldkp, nrows, rows, part, blockIdx.x);
 }
 
+// One block per partial of every task (grid = total), no loop around the
+// body: a task loop led the allocator to one wave per SIMD with AGPR copies,
+// where the one-context kernel holds two waves at under 200 VGPRs.
 template <int J>
 __global__ void __launch_bounds__(64 * gram_tm(J)) k_gram_core_multi(const GramTask *__restrict__ tab,
                                                                       const int32_t *__restrict__ off, int ntask,
                                                                       int total)
 {
-    for (int b = blockIdx.x; b < total; b += gridDim.x) {
-        const int t = task_of(off, ntask, b);
-        const GramTask tk = tab[t];
-        gram_core_body<J>(tk.rb, tk.ldrb, tk.kp, tk.ldkp, tk.nrows, tk.rows, tk.part, b - off[t]);
-        __syncthreads();   // the staged rows in LDS are reused by the next partial
-    }
+    const int b = blockIdx.x;
+    if (b >= total) return;
+    const int t = task_of(off, ntask, b);
+    const GramTask tk = tab[t];
+    gram_core_body<J>(tk.rb, tk.ldrb, tk.kp, tk.ldkp, tk.nrows, tk.rows, tk.part, b - off[t]);
 }
 
 // Rows per partial of the core Gram product (as gram_rows, TM waves a block).
@@ -989,18 +991,18 @@ struct SolveTask {
     int32_t reg;
 };
 
-// one block per context
-template <int J>
+// One block per context (grid = ntask); a launch solves the contexts of
+// regulariser REG and leaves the others to the launch for theirs.  One body
+// per kernel and no loop around it, as in k_slabsolve: both bodies in one
+// kernel, or a task loop, spilled to scratch at J = 9, 10.
+template <int J, int REG>
 __global__ void __launch_bounds__(64) k_slabsolve_multi(const SolveTask *__restrict__ tab, int ntask)
 {
-    for (int t = blockIdx.x; t < ntask; t += gridDim.x) {
-        const SolveTask tk = tab[t];
-        if (tk.reg == VEST_REG_LF)
-            slabsolve_body<J, VEST_REG_LF>(tk.gram, tk.core, tk.cmask, tk.base, tk.lambda, tk.dprev, tk.hdiag);
-        else
-            slabsolve_body<J, VEST_REG_L1>(tk.gram, tk.core, tk.cmask, tk.base, tk.lambda, tk.dprev, tk.hdiag);
-        __syncthreads();   // LDS of the solve is reused by the next context
-    }
+    const int t = blockIdx.x;
+    if (t >= ntask) return;
+    const SolveTask tk = tab[t];
+    if (tk.reg != REG) return;   // uniform over the block
+    slabsolve_body<J, REG>(tk.gram, tk.core, tk.cmask, tk.base, tk.lambda, tk.dprev, tk.hdiag);
 }
 
 // SSE after the core sweep without applying its last slab's change D to the
@@ -1349,6 +1351,8 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
     const size_t o_sse = ba.add(sse.data(), sizeof(SseTask) * n);
     if (ba.overflow) return false;
     const bool lag = nslab > 1;   // as in core_pass_t
+    int nlf = 0;   // contexts with the L_F regulariser (the rest L_1)
+    for (int i = 0; i < n; ++i) nlf += cs[i]->d.reg == VEST_REG_LF ? 1 : 0;
     const BatchArena B = ba;
     const int ncol = (int)col.size();
     const int tcol = coloff.back(), tkp = kpoff[n], tslab = soff[n], tsl = sloff[n], tgr = groff[n], tgs = gsoff[n];
@@ -1372,11 +1376,16 @@ static bool plan_core_batch_t(vest_ctx *const *cs, int n, bool fused, hipStream_
             if (tsl > 0)
                 hipLaunchKernelGGL(k_slab_long_multi<nacc_vc(J)>, dim3(grid(tsl)), dim3(64), 0, st,
                                    B.dptr<SlabLongTask>(o_sl), B.dptr<int32_t>(o_sloff), n, tsl);
-            hipLaunchKernelGGL(k_gram_core_multi<J>, dim3(grid(tgr)), dim3(64 * gram_tm(J)), 0, st,
+            hipLaunchKernelGGL(k_gram_core_multi<J>, dim3(tgr), dim3(64 * gram_tm(J)), 0, st,
                                B.dptr<GramTask>(o_gr), B.dptr<int32_t>(o_groff), n, tgr);
             hipLaunchKernelGGL(k_gramsum_core_multi<J>, dim3(grid(tgs)), dim3(1024), 0, st, B.dptr<GsumTask>(o_gs),
                                B.dptr<int32_t>(o_gsoff), n, tgs);
-            hipLaunchKernelGGL(k_slabsolve_multi<J>, dim3(grid(n)), dim3(64), 0, st, B.dptr<SolveTask>(o_solve[s]), n);
+            if (nlf > 0)
+                hipLaunchKernelGGL((k_slabsolve_multi<J, VEST_REG_LF>), dim3(n), dim3(64), 0, st,
+                                   B.dptr<SolveTask>(o_solve[s]), n);
+            if (nlf < n)
+                hipLaunchKernelGGL((k_slabsolve_multi<J, VEST_REG_L1>), dim3(n), dim3(64), 0, st,
+                                   B.dptr<SolveTask>(o_solve[s]), n);
         }
         if (lag)
             hipLaunchKernelGGL(k_sse_lag_multi<J>, dim3(grid(n)), dim3(1024), 0, st, B.dptr<SseTask>(o_sse), n);
