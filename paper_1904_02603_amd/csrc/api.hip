@@ -277,11 +277,42 @@ static int ensure_residual(vest_ctx *c)
 // Live partition of the layouts once marks have changed (before a factor
 // sweep or the factor keys read klive).  It moves entries of the core layout,
 // so the residual and its slot copy must be formed again.
+// Fraction of dead entries in the worst mode layout if the marks were spread
+// at random: a mode-n entry is dead when one of its other-mode rows is fully
+// marked, and a row of J elements of a factor with marked fraction f is fully
+// marked with probability f^J.
+static double dead_estimate(const vest_ctx *c)
+{
+    double p[VEST_MAX_ORDER];
+    for (int k = 0; k < c->N; ++k) {
+        const double f = (double)c->marked_fac[k] / ((double)c->d.dims[k] * c->J);
+        p[k] = std::pow(f, c->J);
+    }
+    double worst = 0.0;
+    for (int n = 0; n < c->N; ++n) {
+        double alive = 1.0;
+        for (int k = 0; k < c->N; ++k)
+            if (k != n) alive *= 1.0 - p[k];
+        worst = std::max(worst, 1.0 - alive);
+    }
+    return worst;
+}
+
+// The partition costs about one gather sweep per mode, and skipping it is
+// exact: marks never clear, so the steps past an older partition's klive hold
+// dead entries still.  It runs when the estimate of dead entries has grown by
+// kLiveStep since the last partition (a VeST^man ramp partitions a few times,
+// not after every prune step).
+static constexpr double kLiveStep = 0.1;
+
 static int ensure_live(vest_ctx *c, hipStream_t st)
 {
     if (!c->live_stale) return VEST_OK;
+    const double est = dead_estimate(c);
+    if (est < c->live_dead_est + kLiveStep) return VEST_OK;   // stays stale: re-checked after more marks
     CALL_HIP(c, launch_live_partition(c, st), "live partition");
     c->live_stale = false;
+    c->live_dead_est = est;
     c->e_valid = false;
     c->ms_valid = false;
     c->e_lag = false;
@@ -414,7 +445,10 @@ int vest_init(const vest_desc *desc, void *stream, const int32_t *idx, const dou
     if (he == hipSuccess) he = hipMemsetAsync(c->rowbuf, 0, c->d.dims[c->N - 1] * c->ldrb * 8, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) { int r = device_error(nullptr, he, "masks"); delete c; return r; }
-    for (int n = 0; n < c->N; ++n) c->marked_fac[n] = hc[n];
+    for (int n = 0; n < c->N; ++n) {
+        c->marked_fac[n] = hc[n];
+        if (hc[n] > 0) c->live_stale = true;   // rows may start fully marked
+    }
     c->marked_core = hc[c->N];
     c->core_version = 1;
     for (int n = 0; n < c->N; ++n) c->ag_valid[n] = false;
@@ -653,7 +687,10 @@ int vest_compact(vest_ctx *c, int64_t *live_out)
     c->e_valid = false;
     c->ms_valid = false;
     c->hdiag_valid = false;
-    c->live_stale = true;   // the rebuilt layouts start with every step live
+    // every entry left is live in every layout (none has a fully marked row)
+    // and the rebuilt layouts start with every step live
+    c->live_stale = false;
+    c->live_dead_est = dead_estimate(c);
     return VEST_OK;
 }
 

@@ -247,7 +247,8 @@ struct vest_ctx {
     uint64_t gp_version[VEST_MAX_ORDER] = {};
     bool ag_valid[VEST_MAX_ORDER] = {};
     bool e_valid = false;
-    bool live_stale = true;           // marks changed since the layouts' live partition
+    bool live_stale = false;          // marks changed since the layouts' live partition
+    double live_dead_est = 0.0;       // dead-entry estimate at that partition (ensure_live)
     // e lacks the change of the core sweep's last slab (held in dprev); the
     // SSE it would have is in sse_lag, and the change is applied to e only
     // when something reads e
