@@ -486,16 +486,32 @@ hipError_t launch_compact(vest_ctx *c, int32_t **idx_out, double **val_out, int6
 // result.  Padding slots count as dead and already sit at the end.
 constexpr int kLiveMaxK = 16;
 
+// LDS bytes of one wave's staging: its K <= kLiveMaxK steps of indices,
+// canonical id and value, one column per lane
 template <int N, typename T>
-__global__ void __launch_bounds__(256) k_live_partition(WaveInfo *__restrict__ waves, int nwaves, OidxArg oidx,
-                                                        T *__restrict__ xval, int32_t *__restrict__ perm,
-                                                        MaskArg masks, uint32_t full)
+constexpr size_t live_lds_bytes() { return (size_t)kLiveMaxK * kWave * ((N - 1) * 4 + 4 + sizeof(T)); }
+
+// One wave per block.  Each lane reads its K slots, decides which entries are
+// live, and places every entry at its new step in an LDS column of its own
+// (a dynamically indexed per-lane array; no lane reads another's column).  It
+// then writes back in step order, so each store of the wave covers one
+// contiguous row of 64 slots, and only from the lane's first moved step on
+// (a slot keeps its entry up to the lane's first dead one).
+template <int N, typename T>
+__global__ void __launch_bounds__(kWave) k_live_partition(WaveInfo *__restrict__ waves, int nwaves, OidxArg oidx,
+                                                          T *__restrict__ xval, int32_t *__restrict__ perm,
+                                                          MaskArg masks, uint32_t full)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    extern __shared__ __align__(16) char smem[];
+    const int lane = threadIdx.x;
+    const int w = blockIdx.x;
     if (w >= nwaves) return;
     const WaveInfo wi = waves[w];
-    const int K = wi.K < kLiveMaxK ? wi.K : kLiveMaxK;
+    if (wi.K > kLiveMaxK) {   // not met with lane targets <= 16; such a wave keeps every step
+        if (lane == 0) waves[w].klive = wi.K;
+        return;
+    }
+    const int K = wi.K;
     int32_t id[kLiveMaxK][N - 1], pv[kLiveMaxK];
     T xv[kLiveMaxK];
     bool live[kLiveMaxK];
@@ -516,17 +532,29 @@ __global__ void __launch_bounds__(256) k_live_partition(WaveInfo *__restrict__ w
             nlive += ok ? 1 : 0;
         }
     }
-    int nl = 0, nd = nlive;
+    T *sx = reinterpret_cast<T *>(smem);                                         // [kLiveMaxK][64]
+    int32_t *sp = reinterpret_cast<int32_t *>(smem + (size_t)kLiveMaxK * kWave * sizeof(T));   // [kLiveMaxK][64]
+    int32_t *si = sp + kLiveMaxK * kWave;                                        // [N-1][kLiveMaxK][64]
+    int nl = 0, nd = nlive, first = K;
 #pragma unroll
     for (int k = 0; k < kLiveMaxK; ++k) {
         if (k < K) {
             const int dst = live[k] ? nl++ : nd++;
-            const int64_t sl = wi.base + (int64_t)dst * kWave + lane;
+            if (dst != k && k < first) first = k;
+            const int c = dst * kWave + lane;
+            sx[c] = xv[k];
+            sp[c] = pv[k];
 #pragma unroll
-            for (int m = 0; m < N - 1; ++m) oidx.p[m][sl] = id[k][m];
-            xval[sl] = xv[k];
-            perm[sl] = pv[k];
+            for (int m = 0; m < N - 1; ++m) si[m * kLiveMaxK * kWave + c] = id[k][m];
         }
+    }
+    for (int k = first; k < K; ++k) {
+        const int c = k * kWave + lane;
+        const int64_t sl = wi.base + (int64_t)k * kWave + lane;
+#pragma unroll
+        for (int m = 0; m < N - 1; ++m) oidx.p[m][sl] = si[m * kLiveMaxK * kWave + c];
+        xval[sl] = sx[c];
+        perm[sl] = sp[c];
     }
     int kl = nlive;
 #pragma unroll
@@ -550,13 +578,12 @@ static hipError_t live_partition_n(vest_ctx *c, hipStream_t st)
             oa.p[m] = L.oidx[m];
             ma.p[m] = c->fmask[m < n ? m : m + 1];
         }
-        const int blocks = (L.nwaves + 3) / 4;
         if (c->f32)
-            hipLaunchKernelGGL((k_live_partition<N, float>), dim3(blocks), dim3(256), 0, st, L.waves, L.nwaves, oa,
-                               reinterpret_cast<float *>(L.xval), L.perm, ma, full);
+            hipLaunchKernelGGL((k_live_partition<N, float>), dim3(L.nwaves), dim3(kWave), (live_lds_bytes<N, float>()),
+                               st, L.waves, L.nwaves, oa, reinterpret_cast<float *>(L.xval), L.perm, ma, full);
         else
-            hipLaunchKernelGGL((k_live_partition<N, double>), dim3(blocks), dim3(256), 0, st, L.waves, L.nwaves, oa,
-                               reinterpret_cast<double *>(L.xval), L.perm, ma, full);
+            hipLaunchKernelGGL((k_live_partition<N, double>), dim3(L.nwaves), dim3(kWave), (live_lds_bytes<N, double>()),
+                               st, L.waves, L.nwaves, oa, reinterpret_cast<double *>(L.xval), L.perm, ma, full);
     }
     return hipGetLastError();
 }
